@@ -1,0 +1,216 @@
+/*
+ * safegpu.h -- C ABI of the contract-checked, fused collection library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The calls follow the library's problem statement: create a collection (from_array,
+ * Section 3.2 / Table 2), compose operations with agents (project, filter, reductions,
+ * vector and matrix arithmetic, Sections 3.2-3.4), attach require/ensure clauses built from
+ * range queries (for_all, exists, is_sorted, sums; Section 4), and trigger execution
+ * (scalar query, to_array, update; Section 5).  Composition is lazy: nothing runs on the GPU
+ * until a trigger.  The planner then fuses element-wise operations, filters and reductions
+ * over one index space into a single kernel pass (the barrier and expression fusions of
+ * Figures 2 and 3), and evaluates range contracts inside the same pass.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns sg_status; results are written through out-parameters only when
+ *     the call returns SG_OK (or a contract status, see sg_program_execute).
+ *   - Device pointers are HIP device addresses on the context's device; host pointers are
+ *     ordinary host memory.  Sizes are element counts (int64), never bytes, unless named
+ *     *_bytes.
+ *   - Handles (sg_ctx, sg_node, sg_fn, sg_pred, sg_program, sg_batch) are owned by the
+ *     caller and released with the matching *_release / *_destroy call.  A derived node
+ *     holds references to its operands, a program to its roots and contract operands, so
+ *     operands may be released early.
+ *   - Misuse (NULL handle, wrong element type, mismatched counts) returns an SG_E_* code
+ *     and never aborts; sg_last_error() then describes it.  HIP runtime failures map to
+ *     SG_E_DEVICE.
+ *   - Indices reported by contracts are 0-based int64; -1 means "none".
+ *   - All device work is ordered on the stream given to sg_ctx_create; calls that return
+ *     host-visible results synchronize that stream.  A context is not thread-safe.
+ */
+#ifndef SAFEGPU_H
+#define SAFEGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sg_status {
+    SG_OK = 0,
+    SG_E_INVALID = 1,      /* bad argument or handle */
+    SG_E_SHAPE = 2,        /* built-in scalar contract: counts / dimensions disagree */
+    SG_E_DTYPE = 3,        /* operation not defined on this element type */
+    SG_E_OOM = 4,          /* device or host allocation failed */
+    SG_E_DEVICE = 5,       /* HIP runtime error or device-side failure */
+    SG_E_STATE = 6,        /* value not available (not computed, or unpublished) */
+    SG_E_UNSUPPORTED = 7,  /* a chain the planner cannot place (limits exceeded) */
+    SG_PRE_VIOLATED = 16,  /* a require clause failed: the body's outputs are not published */
+    SG_POST_VIOLATED = 17  /* an ensure clause failed: outputs exist, the clause is flagged */
+} sg_status;
+
+typedef enum sg_dtype { SG_F32 = 1, SG_I32 = 2, SG_I64 = 3, SG_F64 = 4 } sg_dtype;
+
+/* Monitoring modes of Section 6.3 without class invariants (this library has none). */
+typedef enum sg_mode { SG_MODE_OFF = 0, SG_MODE_PRE = 1, SG_MODE_PRE_POST = 2 } sg_mode;
+
+/* Element functions (agents of type FUNCTION, Section 3.2). */
+typedef enum sg_fn_kind {
+    SG_FN_SQUARE = 1, SG_FN_NEG = 2, SG_FN_ABS = 3, SG_FN_SQRT = 4, SG_FN_SQRT_ABS = 5,
+    SG_FN_EXP = 6, SG_FN_EXP_NEG_SQ = 7, SG_FN_I2F = 8
+} sg_fn_kind;
+
+typedef enum sg_cmp { SG_LT = 0, SG_LE = 1, SG_GT = 2, SG_GE = 3, SG_EQ = 4, SG_NE = 5 } sg_cmp;
+typedef enum sg_binop { SG_ADD = 0, SG_SUB = 1, SG_MUL = 2 } sg_binop;
+typedef enum sg_red { SG_SUM = 0, SG_MIN = 1, SG_MAX = 2, SG_AVG = 3, SG_COUNT = 4 } sg_red;
+typedef enum sg_clause { SG_REQUIRE = 0, SG_ENSURE = 1 } sg_clause;
+typedef enum sg_quant { SG_FOR_ALL = 0, SG_EXISTS = 1 } sg_quant;
+
+typedef struct sg_ctx_s* sg_ctx;
+typedef struct sg_node_s* sg_node;
+typedef struct sg_fn_s* sg_fn;
+typedef struct sg_pred_s* sg_pred;
+typedef struct sg_program_s* sg_program;
+typedef struct sg_batch_s* sg_batch;
+
+/* One verdict per contract clause of a program, in declaration order. */
+typedef struct sg_verdict {
+    int32_t contract_id;  /* id returned when the clause was attached */
+    int32_t kind;         /* SG_REQUIRE or SG_ENSURE */
+    int32_t holds;        /* 1 holds, 0 violated, -1 not evaluated (mode, or body not run) */
+    int32_t check;        /* SG_CHECK_* */
+    int64_t first_index;  /* first violating (for_all, sorted) / witnessing (exists) index,
+                             first violating row (product); -1 if none */
+    double measure;       /* product: max |e_i|/b_i; close: |s - s64|; else 0 */
+} sg_verdict;
+
+enum { SG_CHECK_FOR_ALL = 0, SG_CHECK_EXISTS = 1, SG_CHECK_SORTED = 2, SG_CHECK_CLOSE = 3,
+       SG_CHECK_PRODUCT = 4 };
+
+/* ---- context ---------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the null
+ * stream) on which all work is enqueued.  Mode defaults to SG_MODE_PRE_POST, fusion on. */
+sg_status sg_ctx_create(int device, void* hip_stream, sg_ctx* out);
+sg_status sg_ctx_destroy(sg_ctx ctx);
+sg_status sg_ctx_set_mode(sg_ctx ctx, sg_mode mode);
+/* fused != 0: fuse (default).  fused == 0: the naive plan of Section 5, one kernel per
+ * operation and per contract, every intermediate materialized. */
+sg_status sg_ctx_set_fusion(sg_ctx ctx, int fused);
+/* Launch plan for the streaming kernel: block size (64..1024, multiple of 64) and unroll
+ * (1, 2, 4 or 8: 16-byte loads per lane per input and tile).  0 keeps the default. */
+sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll);
+/* Record the device time of every kernel launch with HIP events on the context stream. */
+sg_status sg_ctx_set_timing(sg_ctx ctx, int on);
+/* Accumulated device time (ms) and launch count of one kernel family since the last reset:
+ * "stream", "gemm", "product_check", "mlp_train", "mlp_infer". */
+sg_status sg_ctx_timing(sg_ctx ctx, const char* kernel, double* total_ms, int64_t* launches);
+sg_status sg_ctx_timing_reset(sg_ctx ctx);
+/* Message for the last error on this context (thread-unsafe, valid until the next call). */
+const char* sg_last_error(sg_ctx ctx);
+
+/* ---- collections (Section 3.2 from_array; Section 3.4 row-major matrices) ------------- */
+
+/* Borrow `n` elements of device memory at `dev` (16-byte alignment gives 128-bit loads).
+ * The caller keeps the memory alive and unmodified while any execution reads it. */
+sg_status sg_vector_wrap(sg_ctx ctx, sg_dtype dtype, void* dev, int64_t n, sg_node* out);
+sg_status sg_matrix_wrap(sg_ctx ctx, sg_dtype dtype, void* dev, int64_t rows, int64_t cols, sg_node* out);
+/* Copy `n` host elements to new device memory owned by the node (from_array). */
+sg_status sg_vector_from_host(sg_ctx ctx, sg_dtype dtype, const void* host, int64_t n, sg_node* out);
+sg_status sg_matrix_from_host(sg_ctx ctx, sg_dtype dtype, const void* host, int64_t rows, int64_t cols, sg_node* out);
+
+/* ---- agents ---------------------------------------------------------------------------- */
+
+/* f32: x -> RN(RN(a*x) + b).  i32: x -> a*x + b modulo 2^32 (a, b truncated to int32). */
+sg_status sg_fn_affine(double a, double b, sg_fn* out);
+sg_status sg_fn_add_c(double c, sg_fn* out);
+sg_status sg_fn_mul_c(double c, sg_fn* out);
+sg_status sg_fn_unary(sg_fn_kind kind, sg_fn* out);
+/* first f, then g */
+sg_status sg_fn_compose(sg_fn f, sg_fn g, sg_fn* out);
+sg_status sg_fn_release(sg_fn f);
+
+/* Comparisons are IEEE comparisons against c rounded to the operand's element type. */
+sg_status sg_pred_cmp(sg_cmp op, double c, sg_pred* out);
+sg_status sg_pred_isfinite(sg_pred* out);
+sg_status sg_pred_in_range(double lo, double hi, sg_pred* out); /* lo <= x <= hi */
+sg_status sg_pred_true(sg_pred* out);
+sg_status sg_pred_and(sg_pred p, sg_pred q, sg_pred* out);
+sg_status sg_pred_or(sg_pred p, sg_pred q, sg_pred* out);
+sg_status sg_pred_not(sg_pred p, sg_pred* out);
+sg_status sg_pred_release(sg_pred p);
+
+/* ---- lazy operations ------------------------------------------------------------------- */
+
+sg_status sg_map(sg_node in, sg_fn f, sg_node* out);                      /* project */
+sg_status sg_zip(sg_node a, sg_node b, sg_binop op, sg_node* out);        /* plus/minus/compwise */
+sg_status sg_filter(sg_node in, sg_pred p, sg_node* out);                 /* stable */
+sg_status sg_reduce(sg_node in, sg_red red, sg_node* out);                /* scalar node */
+sg_status sg_matmul(sg_node A, sg_node B, sg_node* out);                  /* FP32 matrix cores */
+sg_status sg_release(sg_node n);
+
+/* ---- programs: roots plus require/ensure clauses ---------------------------------------- */
+
+sg_status sg_program_create(sg_ctx ctx, sg_program* out);
+sg_status sg_program_add_root(sg_program p, sg_node n);
+/* for_all / exists of predicate `pred` over collection `n`. */
+sg_status sg_program_quant(sg_program p, sg_clause kind, sg_quant q, sg_node n, sg_pred pred, int32_t* id);
+/* non-decreasing order of collection `n`. */
+sg_status sg_program_sorted(sg_program p, sg_clause kind, sg_node n, int32_t* id);
+/* |value(s) - shadow(s)| <= abs_tol + rel_tol * sum|x| for a float sum node s, where the
+ * shadow is the same sum accumulated in float64 in the same pass. */
+sg_status sg_program_close(sg_program p, sg_clause kind, sg_node s, double abs_tol, double rel_tol, int32_t* id);
+/* Product check of C = A B with the nvec x N matrix R of probe vectors (one per row):
+ * |C r - A(B r)|_i <= (gamma_2K + 2^-40) (|A|(|B||r|))_i for every probe and row. */
+sg_status sg_program_product(sg_program p, sg_clause kind, sg_node C, sg_node A, sg_node B, sg_node R, int32_t* id);
+/* Mark `n` as a fusion split point: it is materialized and its consumers start a new pass. */
+sg_status sg_program_split(sg_program p, sg_node n);
+/* Run the program (trigger "update").  Writes up to `cap` verdicts.  Returns SG_OK,
+ * SG_PRE_VIOLATED (outputs unpublished) or SG_POST_VIOLATED, or an error code. */
+sg_status sg_program_execute(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts);
+sg_status sg_program_release(sg_program p);
+
+/* Execute roots without contracts (shorthand for a temporary program). */
+sg_status sg_execute(sg_ctx ctx, const sg_node* roots, int32_t nroots);
+
+/* ---- triggers and results (Section 5: scalar query, to_array) --------------------------- */
+
+/* Scalar node value: f = value as double (a float sum is rounded to binary32 first),
+ * i = integer value (counts, int sums, int min/max).  Executes the node if needed. */
+sg_status sg_scalar_get(sg_node s, double* f, int64_t* i);
+/* float64 shadow of a float sum or avg node (accumulated in float64 in the same pass). */
+sg_status sg_scalar_shadow(sg_node s, double* f64);
+sg_status sg_count(sg_node c, int64_t* n);
+/* Copy a collection to host memory (at most cap elements); *n = its count. */
+sg_status sg_to_host(sg_node c, void* dst, int64_t cap, int64_t* n);
+/* Device address and count of a computed collection (valid until the node is released or
+ * recomputed). */
+sg_status sg_device_ptr(sg_node c, void** dev, int64_t* n);
+
+/* ---- batched execution: many programs in one persistent launch -------------------------- */
+
+/* Plan `n` programs (each a chain with its own contracts) into one launch of the streaming
+ * kernel; programs must contain no matrix product.  The plan and its launch are captured
+ * into a HIP graph when use_graph != 0. */
+sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int use_graph, sg_batch* out);
+/* Launch once (graph replay or direct launch); results are published to the programs' roots
+ * and verdicts. status_out[n] receives each program's status, verdicts are written program
+ * by program in clause order (up to cap). */
+sg_status sg_batch_run(sg_batch b, int32_t* status_out, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts);
+/* Enqueue one launch without reading results back (for timing); sg_batch_run reads them. */
+sg_status sg_batch_launch(sg_batch b);
+sg_status sg_batch_release(sg_batch b);
+
+/* ---- host-side checks of device arithmetic (no GPU needed) ------------------------------ */
+
+/* Evaluate the device code's correctly rounded binary32 exp on the host for n values;
+ * *slow receives how many took the double-double path.  For tests. */
+sg_status sg_host_exp_rn(const float* t, float* out, int64_t n, int64_t* slow);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAFEGPU_H */

@@ -1,0 +1,489 @@
+"""Python binding of the contract-checked fused collection library (libsafegpu.so).
+
+Argument marshalling only: every operation runs in the HIP library.  PyTorch provides the
+device memory (``wrap`` borrows a CUDA tensor) and the stream.  Importing this module does
+not load the library; ``load()`` does and raises if it is missing.
+
+Names follow the C ABI in ``include/safegpu.h``: ``Context.wrap`` (sg_vector_wrap),
+``Node.map`` (sg_map), ``Program.require_for_all`` (sg_program_quant), ...
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsafegpu.so")
+_lib = None
+
+STATUS = {0: "ok", 1: "invalid", 2: "shape", 3: "dtype", 4: "oom", 5: "device", 6: "state",
+          7: "unsupported", 16: "pre_violated", 17: "post_violated"}
+F32, I32, I64, F64 = 1, 2, 3, 4
+DTYPES = {"f32": F32, "i32": I32}
+MODES = {"off": 0, "pre": 1, "pre_post": 2}
+FN_UNARY = {"square": 1, "neg": 2, "abs": 3, "sqrt": 4, "sqrt_abs": 5, "exp": 6, "exp_neg_sq": 7, "i2f": 8}
+CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5}
+BINOP = {"add": 0, "sub": 1, "mul": 2}
+RED = {"sum": 0, "min": 1, "max": 2, "avg": 3, "count": 4}
+CLAUSE = {"require": 0, "ensure": 1}
+CHECKS = {0: "for_all", 1: "exists", 2: "sorted", 3: "close", 4: "product"}
+
+
+class Verdict(ctypes.Structure):
+    _fields_ = [("contract_id", c_int32), ("kind", c_int32), ("holds", c_int32), ("check", c_int32),
+                ("first_index", c_int64), ("measure", c_double)]
+
+    def as_tuple(self):
+        return (self.holds, self.first_index, self.measure)
+
+    def __repr__(self):
+        return (f"Verdict(id={self.contract_id}, {'require' if self.kind == 0 else 'ensure'} "
+                f"{CHECKS.get(self.check)}, holds={self.holds}, first={self.first_index}, measure={self.measure:g})")
+
+
+class SafeGPUError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.status_name = STATUS.get(status, str(status))
+
+
+def _sig(lib):
+    H = c_void_p
+    P = POINTER
+    sigs = {
+        "sg_ctx_create": [c_int, H, P(H)], "sg_ctx_destroy": [H], "sg_ctx_set_mode": [H, c_int],
+        "sg_ctx_set_fusion": [H, c_int], "sg_ctx_set_launch": [H, c_int, c_int], "sg_ctx_set_timing": [H, c_int],
+        "sg_ctx_timing": [H, c_char_p, P(c_double), P(c_int64)], "sg_ctx_timing_reset": [H],
+        "sg_vector_wrap": [H, c_int, H, c_int64, P(H)], "sg_matrix_wrap": [H, c_int, H, c_int64, c_int64, P(H)],
+        "sg_vector_from_host": [H, c_int, H, c_int64, P(H)],
+        "sg_matrix_from_host": [H, c_int, H, c_int64, c_int64, P(H)],
+        "sg_fn_affine": [c_double, c_double, P(H)], "sg_fn_add_c": [c_double, P(H)], "sg_fn_mul_c": [c_double, P(H)],
+        "sg_fn_unary": [c_int, P(H)], "sg_fn_compose": [H, H, P(H)], "sg_fn_release": [H],
+        "sg_pred_cmp": [c_int, c_double, P(H)], "sg_pred_isfinite": [P(H)], "sg_pred_in_range": [c_double, c_double, P(H)],
+        "sg_pred_true": [P(H)], "sg_pred_and": [H, H, P(H)], "sg_pred_or": [H, H, P(H)], "sg_pred_not": [H, P(H)],
+        "sg_pred_release": [H],
+        "sg_map": [H, H, P(H)], "sg_zip": [H, H, c_int, P(H)], "sg_filter": [H, H, P(H)], "sg_reduce": [H, c_int, P(H)],
+        "sg_matmul": [H, H, P(H)], "sg_release": [H],
+        "sg_program_create": [H, P(H)], "sg_program_add_root": [H, H],
+        "sg_program_quant": [H, c_int, c_int, H, H, P(c_int32)], "sg_program_sorted": [H, c_int, H, P(c_int32)],
+        "sg_program_close": [H, c_int, H, c_double, c_double, P(c_int32)],
+        "sg_program_product": [H, c_int, H, H, H, H, P(c_int32)], "sg_program_split": [H, H],
+        "sg_program_execute": [H, P(Verdict), c_int32, P(c_int32)], "sg_program_release": [H],
+        "sg_execute": [H, P(H), c_int32],
+        "sg_scalar_get": [H, P(c_double), P(c_int64)], "sg_scalar_shadow": [H, P(c_double)],
+        "sg_count": [H, P(c_int64)], "sg_to_host": [H, H, c_int64, P(c_int64)], "sg_device_ptr": [H, P(H), P(c_int64)],
+        "sg_batch_create": [H, P(H), c_int32, c_int, P(H)],
+        "sg_batch_run": [H, P(c_int32), P(Verdict), c_int32, P(c_int32)],
+        "sg_batch_launch": [H], "sg_batch_release": [H],
+        "sg_host_exp_rn": [H, H, c_int64, P(c_int64)],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = c_int
+    lib.sg_last_error.argtypes = [H]
+    lib.sg_last_error.restype = c_char_p
+    return lib
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libsafegpu.so (built by build.py).  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_1410_6685_amd/build.py`")
+        _lib = _sig(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _check(st: int, ctx_handle=None, ok=(0,)):
+    if st not in ok:
+        msg = load().sg_last_error(ctx_handle)
+        raise SafeGPUError(st, msg.decode() if msg else "")
+    return st
+
+
+def host_exp_rn(t):
+    """Run the device's correctly rounded exp on the host (numpy float32 in, float32 out)."""
+    import numpy as np
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    out = np.empty_like(t)
+    slow = c_int64()
+    _check(load().sg_host_exp_rn(t.ctypes.data, out.ctypes.data, t.size, byref(slow)))
+    return out, slow.value
+
+
+# ---------------------------------------------------------------------------------------------
+# agents
+
+class Fn:
+    def __init__(self, handle):
+        self.h = handle
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.sg_fn_release(self.h)
+            self.h = None
+
+    @staticmethod
+    def affine(a, b):
+        h = c_void_p(); _check(load().sg_fn_affine(a, b, byref(h))); return Fn(h)
+
+    @staticmethod
+    def add_c(c):
+        h = c_void_p(); _check(load().sg_fn_add_c(c, byref(h))); return Fn(h)
+
+    @staticmethod
+    def mul_c(c):
+        h = c_void_p(); _check(load().sg_fn_mul_c(c, byref(h))); return Fn(h)
+
+    @staticmethod
+    def unary(name):
+        h = c_void_p(); _check(load().sg_fn_unary(FN_UNARY[name], byref(h))); return Fn(h)
+
+    def then(self, g: "Fn"):
+        h = c_void_p(); _check(load().sg_fn_compose(self.h, g.h, byref(h))); return Fn(h)
+
+    @staticmethod
+    def from_spec(fn) -> "Fn":
+        name = fn[0]
+        if name == "affine":
+            return Fn.affine(float(fn[1]), float(fn[2]))
+        if name == "add_c":
+            return Fn.add_c(float(fn[1]))
+        if name == "mul_c":
+            return Fn.mul_c(float(fn[1]))
+        if name == "compose":
+            return Fn.from_spec(fn[1]).then(Fn.from_spec(fn[2]))
+        return Fn.unary(name)
+
+
+class Pred:
+    def __init__(self, handle):
+        self.h = handle
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.sg_pred_release(self.h)
+            self.h = None
+
+    @staticmethod
+    def cmp(op, c):
+        h = c_void_p(); _check(load().sg_pred_cmp(CMP[op], c, byref(h))); return Pred(h)
+
+    @staticmethod
+    def isfinite():
+        h = c_void_p(); _check(load().sg_pred_isfinite(byref(h))); return Pred(h)
+
+    @staticmethod
+    def in_range(lo, hi):
+        h = c_void_p(); _check(load().sg_pred_in_range(lo, hi, byref(h))); return Pred(h)
+
+    @staticmethod
+    def true():
+        h = c_void_p(); _check(load().sg_pred_true(byref(h))); return Pred(h)
+
+    def __and__(self, q):
+        h = c_void_p(); _check(load().sg_pred_and(self.h, q.h, byref(h))); return Pred(h)
+
+    def __or__(self, q):
+        h = c_void_p(); _check(load().sg_pred_or(self.h, q.h, byref(h))); return Pred(h)
+
+    def __invert__(self):
+        h = c_void_p(); _check(load().sg_pred_not(self.h, byref(h))); return Pred(h)
+
+    @staticmethod
+    def from_spec(p) -> "Pred":
+        name = p[0]
+        if name == "cmp":
+            return Pred.cmp(p[1], float(p[2]))
+        if name == "isfinite":
+            return Pred.isfinite()
+        if name == "in_range":
+            return Pred.in_range(float(p[1]), float(p[2]))
+        if name == "true":
+            return Pred.true()
+        if name == "and":
+            return Pred.from_spec(p[1]) & Pred.from_spec(p[2])
+        if name == "or":
+            return Pred.from_spec(p[1]) | Pred.from_spec(p[2])
+        if name == "not":
+            return ~Pred.from_spec(p[1])
+        raise ValueError(name)
+
+
+# ---------------------------------------------------------------------------------------------
+# nodes, programs, context
+
+class Node:
+    def __init__(self, ctx: "Context", handle, keep=None):
+        self.ctx = ctx
+        self.h = handle
+        self._keep = keep  # borrowed tensor kept alive
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.sg_release(self.h)
+            self.h = None
+
+    def _new(self, fn, *args):
+        h = c_void_p()
+        _check(fn(*args, byref(h)), self.ctx.h)
+        return Node(self.ctx, h)
+
+    def map(self, f: Fn):
+        return self._new(load().sg_map, self.h, f.h)
+
+    def zip(self, other: "Node", op: str):
+        return self._new(load().sg_zip, self.h, other.h, BINOP[op])
+
+    def filter(self, p: Pred):
+        return self._new(load().sg_filter, self.h, p.h)
+
+    def reduce(self, red: str):
+        return self._new(load().sg_reduce, self.h, RED[red])
+
+    def matmul(self, other: "Node"):
+        return self._new(load().sg_matmul, self.h, other.h)
+
+    def scalar(self):
+        f, i = c_double(), c_int64()
+        _check(load().sg_scalar_get(self.h, byref(f), byref(i)), self.ctx.h)
+        return f.value, i.value
+
+    def shadow(self):
+        f = c_double()
+        _check(load().sg_scalar_shadow(self.h, byref(f)), self.ctx.h)
+        return f.value
+
+    def count(self):
+        n = c_int64()
+        _check(load().sg_count(self.h, byref(n)), self.ctx.h)
+        return n.value
+
+    def to_host(self, dtype="f32"):
+        import numpy as np
+        n = self.count()
+        out = np.empty(n, dtype=np.float32 if dtype == "f32" else np.int32)
+        m = c_int64()
+        _check(load().sg_to_host(self.h, out.ctypes.data if n else None, n, byref(m)), self.ctx.h)
+        return out
+
+    def device_ptr(self):
+        p, n = c_void_p(), c_int64()
+        _check(load().sg_device_ptr(self.h, byref(p), byref(n)), self.ctx.h)
+        return p.value, n.value
+
+
+class Program:
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+        self.h = c_void_p()
+        _check(load().sg_program_create(ctx.h, byref(self.h)), ctx.h)
+        self._keep = []
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.sg_program_release(self.h)
+            self.h = None
+
+    def add_root(self, n: Node):
+        _check(load().sg_program_add_root(self.h, n.h), self.ctx.h)
+        self._keep.append(n)
+
+    def quant(self, clause: str, quant: str, n: Node, p: Pred) -> int:
+        cid = c_int32()
+        _check(load().sg_program_quant(self.h, CLAUSE[clause], 0 if quant == "for_all" else 1, n.h, p.h, byref(cid)),
+               self.ctx.h)
+        self._keep += [n, p]
+        return cid.value
+
+    def require_for_all(self, n, p): return self.quant("require", "for_all", n, p)
+    def ensure_for_all(self, n, p): return self.quant("ensure", "for_all", n, p)
+    def require_exists(self, n, p): return self.quant("require", "exists", n, p)
+    def ensure_exists(self, n, p): return self.quant("ensure", "exists", n, p)
+
+    def sorted(self, clause: str, n: Node) -> int:
+        cid = c_int32()
+        _check(load().sg_program_sorted(self.h, CLAUSE[clause], n.h, byref(cid)), self.ctx.h)
+        self._keep.append(n)
+        return cid.value
+
+    def close(self, clause: str, s: Node, abs_tol: float, rel_tol: float = 0.0) -> int:
+        cid = c_int32()
+        _check(load().sg_program_close(self.h, CLAUSE[clause], s.h, abs_tol, rel_tol, byref(cid)), self.ctx.h)
+        self._keep.append(s)
+        return cid.value
+
+    def product(self, clause: str, C: Node, A: Node, B: Node, R: Node) -> int:
+        cid = c_int32()
+        _check(load().sg_program_product(self.h, CLAUSE[clause], C.h, A.h, B.h, R.h, byref(cid)), self.ctx.h)
+        self._keep += [C, A, B, R]
+        return cid.value
+
+    def split(self, n: Node):
+        _check(load().sg_program_split(self.h, n.h), self.ctx.h)
+        self._keep.append(n)
+
+    def execute(self, cap: int = 64):
+        """Run the program.  Returns (status name, [Verdict...]); raises on API errors."""
+        buf = (Verdict * cap)()
+        nv = c_int32()
+        st = load().sg_program_execute(self.h, buf, cap, byref(nv))
+        _check(st, self.ctx.h, ok=(0, 16, 17))
+        return STATUS[st], [buf[i] for i in range(min(nv.value, cap))]
+
+
+class Batch:
+    def __init__(self, ctx: "Context", programs: list, use_graph: bool = True):
+        self.ctx = ctx
+        self.programs = programs
+        arr = (c_void_p * len(programs))(*[p.h for p in programs])
+        self.h = c_void_p()
+        _check(load().sg_batch_create(ctx.h, arr, len(programs), int(use_graph), byref(self.h)), ctx.h)
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.sg_batch_release(self.h)
+            self.h = None
+
+    def launch(self):
+        _check(load().sg_batch_launch(self.h), self.ctx.h)
+
+    def run(self, cap_per_program: int = 4):
+        n = len(self.programs)
+        st = (c_int32 * n)()
+        cap = n * cap_per_program
+        buf = (Verdict * cap)()
+        nv = c_int32()
+        _check(load().sg_batch_run(self.h, st, buf, cap, byref(nv)), self.ctx.h)
+        return [STATUS[s] for s in st], [buf[i] for i in range(min(nv.value, cap))]
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.h = c_void_p()
+        _check(load().sg_ctx_create(device, c_void_p(stream.cuda_stream), byref(self.h)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sg_ctx_destroy(self.h)
+            self.h = None
+
+    def set_mode(self, mode: str):
+        _check(load().sg_ctx_set_mode(self.h, MODES[mode]), self.h)
+
+    def set_fusion(self, fused: bool):
+        _check(load().sg_ctx_set_fusion(self.h, int(fused)), self.h)
+
+    def set_launch(self, block: int = 0, unroll: int = 0):
+        _check(load().sg_ctx_set_launch(self.h, block, unroll), self.h)
+
+    def set_timing(self, on: bool):
+        _check(load().sg_ctx_set_timing(self.h, int(on)), self.h)
+
+    def timing(self, kernel: str):
+        ms, n = c_double(), c_int64()
+        _check(load().sg_ctx_timing(self.h, kernel.encode(), byref(ms), byref(n)), self.h)
+        return ms.value, n.value
+
+    def timing_reset(self):
+        _check(load().sg_ctx_timing_reset(self.h), self.h)
+
+    def wrap(self, t, dtype: str | None = None) -> Node:
+        """Borrow a contiguous 1-D or 2-D CUDA tensor (float32 or int32) as a vector/matrix."""
+        import torch
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("wrap needs a contiguous CUDA tensor")
+        dt = {torch.float32: F32, torch.int32: I32}[t.dtype]
+        h = c_void_p()
+        if t.dim() == 2:
+            _check(load().sg_matrix_wrap(self.h, dt, c_void_p(t.data_ptr()), t.shape[0], t.shape[1], byref(h)), self.h)
+        else:
+            _check(load().sg_vector_wrap(self.h, dt, c_void_p(t.data_ptr()), t.numel(), byref(h)), self.h)
+        return Node(self, h, keep=t)
+
+    def from_host(self, a) -> Node:
+        import numpy as np
+        a = np.ascontiguousarray(a)
+        dt = {np.dtype(np.float32): F32, np.dtype(np.int32): I32}[a.dtype]
+        h = c_void_p()
+        if a.ndim == 2:
+            _check(load().sg_matrix_from_host(self.h, dt, a.ctypes.data, a.shape[0], a.shape[1], byref(h)), self.h)
+        else:
+            _check(load().sg_vector_from_host(self.h, dt, a.ctypes.data, a.size, byref(h)), self.h)
+        return Node(self, h)
+
+    def execute(self, *roots: Node):
+        arr = (c_void_p * len(roots))(*[r.h for r in roots])
+        _check(load().sg_execute(self.h, arr, len(roots)), self.h)
+
+
+# ---------------------------------------------------------------------------------------------
+# chain specifications (see workloads): build nodes and a program through the C ABI
+
+class Built:
+    def __init__(self, ctx, nodes, program, contract_ids):
+        self.ctx = ctx
+        self.nodes = nodes
+        self.program = program
+        self.contract_ids = contract_ids
+
+    def __getitem__(self, name):
+        return self.nodes[name]
+
+
+def build_spec(ctx: Context, spec: dict, tensors: dict) -> Built:
+    """Compose the chain of `spec` over the CUDA tensors `tensors` (name -> tensor) and attach
+    its contracts to a program whose roots are spec["outputs"]."""
+    nodes = {}
+    for inp in spec["inputs"]:
+        nodes[inp["name"]] = ctx.wrap(tensors[inp["name"]])
+    for nd in spec["nodes"]:
+        op = nd["op"]
+        if op == "map":
+            nodes[nd["name"]] = nodes[nd["src"]].map(Fn.from_spec(nd["fn"]))
+        elif op == "zip":
+            nodes[nd["name"]] = nodes[nd["a"]].zip(nodes[nd["b"]], nd["binop"])
+        elif op == "filter":
+            nodes[nd["name"]] = nodes[nd["src"]].filter(Pred.from_spec(nd["pred"]))
+        elif op == "reduce":
+            nodes[nd["name"]] = nodes[nd["src"]].reduce(nd["red"])
+        elif op == "matmul":
+            nodes[nd["name"]] = nodes[nd["a"]].matmul(nodes[nd["b"]])
+        else:
+            raise ValueError(op)
+    prog = Program(ctx)
+    for o in spec.get("outputs", []):
+        prog.add_root(nodes[o])
+    ids = []
+    for c in spec.get("contracts", []):
+        chk = c["check"]
+        if chk in ("for_all", "exists"):
+            ids.append(prog.quant(c["kind"], chk, nodes[c["node"]], Pred.from_spec(c["pred"])))
+        elif chk == "sorted":
+            ids.append(prog.sorted(c["kind"], nodes[c["node"]]))
+        elif chk == "close":
+            ids.append(prog.close(c["kind"], nodes[c["node"]], float(c.get("abs_tol", 0.0)), float(c.get("rel_tol", 0.0))))
+        elif chk == "product":
+            ids.append(prog.product(c["kind"], nodes[c["node"]], nodes[c["a"]], nodes[c["b"]], nodes[c["r"]]))
+        else:
+            raise ValueError(chk)
+    return Built(ctx, nodes, prog, ids)
+
+
+def scalar_value(node: Node):
+    """(value, shadow) of a scalar node: value as float (or int for counts/int results)."""
+    f, i = node.scalar()
+    return f, i

@@ -1,0 +1,179 @@
+// Batched execution: many independent programs (each a chain with its own contracts) in one
+// persistent launch of the streaming kernel, optionally captured into a HIP graph.
+//
+// Instances are laid out back to back in one tile space; a tile-to-instance table lets every
+// block find its instance with one load.  Each instance keeps its own accumulators, look-back
+// range and finalization, so results equal those of separate launches.  The batch owns its
+// scratch, so the graph's baked addresses stay valid whatever else runs on the context.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "sg_kernels.h"
+#include "sg_runtime.h"
+
+using namespace sg;
+using namespace sgrt;
+
+hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
+
+struct sg_batch_s {
+    sg_ctx_s* ctx = nullptr;
+    std::vector<sg_program_s*> progs;
+    Scratch scratch;
+    void* table = nullptr;           // InstDesc[] | SgOp[] | int32 tile_inst[]
+    StreamArgs args;
+    int grid = 1, block = 256, unroll = 2;
+    int64_t total_tiles = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    InstResult* host = nullptr;
+};
+
+static sg_status batch_free(sg_batch_s* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->table) (void)hipFree(b->table);
+    if (b->scratch.base) (void)hipFree(b->scratch.base);
+    if (b->host) (void)hipHostFree(b->host);
+    for (auto* p : b->progs) (void)sg_program_release(p);
+    delete b;
+    return SG_OK;
+}
+
+extern "C" {
+
+sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int use_graph, sg_batch* out) {
+    if (!ctx || !out || n <= 0 || !progs) return fail(ctx, SG_E_INVALID, "batch_create: bad argument");
+    auto* b = new sg_batch_s();
+    b->ctx = ctx;
+    b->block = ctx->block;
+    b->unroll = ctx->unroll;
+    const int64_t tile_elems = (int64_t)b->block * 4 * b->unroll;
+    std::vector<InstDesc> descs;
+    std::vector<SgOp> ops;
+    std::vector<int32_t> tile_inst;
+    for (int i = 0; i < n; ++i) {
+        sg_program_s* P = progs[i];
+        if (!P || P->ctx != ctx) { batch_free(b); return fail(ctx, SG_E_INVALID, "batch_create: bad program"); }
+        ++P->refs;
+        b->progs.push_back(P);
+        sg_status st = build_plan(P, &P->plan);
+        if (st != SG_OK) { batch_free(b); return st; }
+        Plan& plan = P->plan;
+        if (plan.insts.size() != 1 || plan.steps.size() != 1)
+            { batch_free(b); return fail(ctx, SG_E_UNSUPPORTED, "batch: every program must plan to exactly one streaming pass"); }
+        for (auto* m : plan.mats)
+            if ((st = alloc_output(ctx, m)) != SG_OK) { batch_free(b); return st; }
+        InstPlan& ip = plan.insts[0];
+        if (ip.n_src) { batch_free(b); return fail(ctx, SG_E_UNSUPPORTED, "batch: sources must have host-known lengths"); }
+        ip.result_index = i;
+        const int64_t nt = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);
+        InstDesc d;
+        fill_inst(ip, d, b->total_tiles, nt, (int)ops.size());
+        descs.push_back(d);
+        ops.insert(ops.end(), ip.prog.begin(), ip.prog.end());
+        for (int64_t t = 0; t < nt; ++t) tile_inst.push_back(i);
+        b->total_tiles += nt;
+    }
+    sg_status st = alloc_scratch(ctx, b->scratch, b->total_tiles, n);
+    if (st != SG_OK) { batch_free(b); return st; }
+    const size_t db = descs.size() * sizeof(InstDesc), ob = ops.size() * sizeof(SgOp), tb = tile_inst.size() * 4;
+    const size_t off_o = (db + 255) & ~(size_t)255, off_t = (off_o + ob + 255) & ~(size_t)255;
+    if (hipMalloc(&b->table, off_t + tb) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_OOM, "batch table"); }
+    char* base = (char*)b->table;
+    if (hipMemcpy(base, descs.data(), db, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + off_o, ops.data(), ob, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + off_t, tile_inst.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
+        batch_free(b);
+        return fail(ctx, SG_E_DEVICE, "batch table upload");
+    }
+    if (hipHostMalloc((void**)&b->host, (size_t)n * sizeof(InstResult), hipHostMallocDefault) != hipSuccess) {
+        batch_free(b);
+        return fail(ctx, SG_E_OOM, "batch host results");
+    }
+    StreamArgs& a = b->args;
+    std::memset(&a, 0, sizeof(a));
+    a.insts = (const InstDesc*)base;
+    a.progs = (const SgOp*)(base + off_o);
+    a.tile_inst = (const int32_t*)(base + off_t);
+    a.total_tiles = b->total_tiles;
+    a.acc = b->scratch.acc;
+    a.tile_sums = b->scratch.tile_sums;
+    a.lookback = b->scratch.lookback;
+    a.counters = b->scratch.counters;
+    a.epoch = b->scratch.epoch;
+    a.results = b->scratch.results;
+    a.ninst = n;
+    b->grid = stream_grid(ctx, b->total_tiles, false);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "batch sync"); }
+    if (use_graph) {
+        // the graph holds only the kernel node (no memset nodes): the kernel leaves its
+        // scratch ready for the next replay
+        hipStream_t cs = ctx->stream;
+        bool own = false;
+        if (!cs) {
+            if (hipStreamCreate(&cs) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "capture stream"); }
+            own = true;
+        }
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = sg_launch_stream(a, b->unroll, false, b->grid, b->block, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
+        if (own) (void)hipStreamDestroy(cs);
+        if (e != hipSuccess || e2 != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "graph capture failed"); }
+        if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+            { batch_free(b); return fail(ctx, SG_E_DEVICE, "graph instantiate failed"); }
+    }
+    *out = b;
+    return SG_OK;
+}
+
+sg_status sg_batch_launch(sg_batch b) {
+    if (!b) return fail(nullptr, SG_E_INVALID, "batch_launch: NULL batch");
+    sg_ctx_s* ctx = b->ctx;
+    if (b->exec) SG_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
+    else SG_HIP(ctx, sg_launch_stream(b->args, b->unroll, false, b->grid, b->block, ctx->stream));
+    return SG_OK;
+}
+
+sg_status sg_batch_run(sg_batch b, int32_t* status_out, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+    if (!b) return fail(nullptr, SG_E_INVALID, "batch_run: NULL batch");
+    if (cap < 0 || (cap > 0 && !verdicts)) return fail(b->ctx, SG_E_INVALID, "batch_run: bad verdict buffer");
+    sg_ctx_s* ctx = b->ctx;
+    sg_status st = sg_batch_launch(b);
+    if (st != SG_OK) return st;
+    const int n = (int)b->progs.size();
+    SG_HIP(ctx, hipMemcpyAsync(b->host, b->scratch.results, (size_t)n * sizeof(InstResult), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < n; ++i)
+        if (b->host[i].err) return fail(ctx, SG_E_DEVICE, "batched kernel reported a device-side failure");
+    int32_t nv = 0;
+    std::vector<sg_verdict> V;
+    std::vector<InstResult> one(1);
+    for (int i = 0; i < n; ++i) {
+        sg_program_s* P = b->progs[i];
+        one[0] = b->host[i];
+        P->plan.insts[0].result_index = 0;
+        sg_status ps = assemble_verdicts(P, one.data(), V);
+        publish_inst(P->plan.insts[0], one[0], ps != SG_PRE_VIOLATED);
+        P->plan.insts[0].result_index = i;
+        if (status_out) status_out[i] = ps;
+        for (auto& v : V) {
+            if (nv < cap) verdicts[nv] = v;
+            ++nv;
+        }
+    }
+    if (nverdicts) *nverdicts = nv;
+    return SG_OK;
+}
+
+sg_status sg_batch_release(sg_batch b) {
+    if (!b) return SG_E_INVALID;
+    (void)hipStreamSynchronize(b->ctx->stream);
+    return batch_free(b);
+}
+
+}  // extern "C"

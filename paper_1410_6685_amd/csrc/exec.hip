@@ -1,0 +1,536 @@
+// Executor: binds a plan to device memory, launches its steps on the context stream, reads
+// the per-pass results back once, and publishes values and contract verdicts.
+//
+// Contract protocol (Section 4): requires are checked on entry and ensures on exit.  All
+// active clauses of a pass are evaluated in the same pass as the body (the operations are
+// pure, so evaluating a require speculatively changes nothing).  A failing require means
+// the body "did not run": its outputs are not published and the ensures are reported as not
+// evaluated.  The violation returned is the first failing clause in declaration order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sg_kernels.h"
+#include "sg_runtime.h"
+
+using namespace sg;
+
+hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
+hipError_t sg_launch_gemm_f32(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t K, hipStream_t s);
+hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
+                                   int64_t N, int64_t K, int64_t nvec, double tol, double* work, InstResult* res,
+                                   hipStream_t s);
+int sg_stream_occupancy(int unroll, bool inl, int block);
+
+namespace sgrt {
+
+namespace {
+
+struct Timed {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+hipEvent_t get_event(sg_ctx_s* ctx, size_t i) {
+    while (ctx->events.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->events.push_back(e);
+    }
+    return ctx->events[i];
+}
+
+
+float key_to_float(int32_t k) {
+    const uint32_t b = k >= 0 ? (uint32_t)k : ((uint32_t)k ^ 0x7FFFFFFFu);
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+}  // namespace
+
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl) {
+    auto key = std::make_pair(ctx->unroll * (inl ? 1 : -1), ctx->block);
+    auto it = ctx->occupancy.find(key);
+    int nb;
+    if (it != ctx->occupancy.end()) {
+        nb = it->second;
+    } else {
+        nb = sg_stream_occupancy(ctx->unroll, inl, ctx->block);
+        ctx->occupancy[key] = nb;
+    }
+    const int64_t cap = (int64_t)nb * ctx->num_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cap));
+}
+
+sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n) {
+    const size_t bytes = (size_t)std::max<int64_t>(n->n, 1) * 4;
+    if (n->dev && n->owned && n->bytes >= bytes) return SG_OK;
+    if (n->dev && n->owned) dev_free(ctx, n->dev);
+    n->dev = dev_alloc(ctx, bytes);
+    if (!n->dev) return fail(ctx, SG_E_OOM, "output allocation failed");
+    n->owned = true;
+    n->bytes = bytes;
+    return SG_OK;
+}
+
+// Fill one pass's instance descriptor from the plan and the nodes' current storage.
+void fill_inst(const InstPlan& ip, InstDesc& d, int64_t tile0, int64_t ntiles, int prog_off) {
+    std::memset(&d, 0, sizeof(d));
+    bool aligned = true;
+    for (size_t k = 0; k < ip.sources.size(); ++k) {
+        d.in[k] = ip.sources[k]->dev;
+        aligned = aligned && ((uintptr_t)d.in[k] % 16 == 0);
+    }
+    for (size_t k = 0; k < ip.outs.size(); ++k) {
+        d.out[k] = ip.outs[k]->dev;
+        aligned = aligned && ((uintptr_t)d.out[k] % 16 == 0);
+    }
+    d.n = ip.n;
+    d.n_dev = ip.n_src ? ip.n_src->count_dev : nullptr;
+    d.tile0 = tile0;
+    d.ntiles = ntiles;
+    d.prog_off = prog_off;
+    d.prog_len = (int32_t)ip.prog.size();
+    d.nin = (int32_t)ip.sources.size();
+    d.scan_space = ip.scan_space;
+    d.nsum = ip.nsum;
+    d.nslots = (int32_t)ip.slot_kind.size();
+    d.count_slot = ip.count_slot;
+    d.flags = aligned ? 1 : 0;
+    for (size_t k = 0; k < ip.slot_kind.size(); ++k) d.slot_kind[k] = ip.slot_kind[k];
+}
+
+// Publish the results of one pass (after the read-back).
+void publish_inst(const InstPlan& ip, const InstResult& r, bool publish_values) {
+    for (auto& so : ip.scalars) {
+        sg_node_s* n = so.node;
+        const sg_node_s* src = n->src[0];
+        const bool f = src->dtype == SG_F32;
+        switch (n->red) {
+            case SG_SUM:
+                if (f) {
+                    n->f64 = r.sum[so.sum];
+                    n->fval = (double)(float)n->f64;
+                    n->ival = 0;
+                } else {
+                    n->ival = r.slot[so.slot];
+                    n->fval = n->f64 = (double)n->ival;
+                }
+                break;
+            case SG_AVG: {
+                const int64_t cnt = r.slot[so.count_slot];
+                const double s = f ? r.sum[so.sum] : (double)r.slot[so.slot];
+                n->f64 = cnt > 0 ? s / (double)cnt : NAN;
+                n->fval = f ? (double)(float)n->f64 : n->f64;
+                n->ival = cnt;
+            } break;
+            case SG_MAX: case SG_MIN: {
+                const uint32_t e = (uint32_t)r.slot[so.slot];
+                const bool mx = n->red == SG_MAX;
+                if (e == 0) {  // empty collection: identity element
+                    if (f) n->fval = mx ? -INFINITY : INFINITY;
+                    n->ival = mx ? INT32_MIN : INT32_MAX;
+                    if (!f) n->fval = (double)n->ival;
+                } else {
+                    const uint32_t u = mx ? e : ~e;
+                    const int32_t k = (int32_t)(u ^ 0x80000000u);
+                    if (f) {
+                        const bool nan = mx ? (k == INT32_MAX) : (k == INT32_MIN);
+                        n->fval = nan ? NAN : (double)key_to_float(k);
+                        n->ival = 0;
+                    } else {
+                        n->ival = k;
+                        n->fval = (double)k;
+                    }
+                }
+                n->f64 = n->fval;
+            } break;
+            case SG_COUNT:
+                n->ival = r.slot[so.slot];
+                n->fval = n->f64 = (double)n->ival;
+                break;
+        }
+        n->state = publish_values ? ST_COMPUTED : ST_UNPUBLISHED;
+    }
+    for (auto* o : ip.outs) {
+        o->state = publish_values ? ST_COMPUTED : ST_UNPUBLISHED;
+        o->count = ip.base_count_slot >= 0 ? r.slot[ip.base_count_slot] : o->n;
+    }
+    for (auto* o : ip.compacted) o->count = r.scan_count;
+}
+
+// Verdicts of every clause from the read-back results; returns the program status.
+sg_status assemble_verdicts(sg_program_s* P, const InstResult* results, std::vector<sg_verdict>& V) {
+    const Plan& plan = P->plan;
+    const int nc = (int)P->contracts.size();
+    V.assign(nc, sg_verdict{});
+    for (int i = 0; i < nc; ++i) {
+        V[i].contract_id = P->contracts[i].id;
+        V[i].kind = P->contracts[i].kind;
+        V[i].check = P->contracts[i].check;
+        V[i].holds = -1;
+        V[i].first_index = -1;
+        V[i].measure = 0.0;
+    }
+    for (auto& ip : plan.insts) {
+        const InstResult& r = results[ip.result_index];
+        for (auto& ch : ip.checks) {
+            const uint64_t e = (uint64_t)r.slot[ch.slot];
+            const int check = P->contracts[ch.contract].check;
+            sg_verdict& v = V[ch.contract];
+            const bool found = e != 0;
+            v.first_index = found ? (int64_t)~e : -1;
+            v.holds = check == SG_CHECK_EXISTS ? (found ? 1 : 0) : (found ? 0 : 1);
+        }
+    }
+    // close contracts: need the scalar's float64 shadow and |x| sum
+    for (auto& ip : plan.insts) {
+        const InstResult& r = results[ip.result_index];
+        for (auto& so : ip.scalars) {
+            for (int ci : plan.active) {
+                const Contract& c = P->contracts[ci];
+                if (c.check != SG_CHECK_CLOSE || c.node != so.node) continue;
+                const double s64 = r.sum[so.sum];
+                const double s32 = (double)(float)s64;
+                double asum = 0.0;
+                for (auto& a : ip.abssums)
+                    if (a.contract == ci) asum = r.sum[a.sum];
+                const double dev = std::fabs(s32 - s64);
+                V[ci].measure = dev;
+                V[ci].holds = dev <= c.abs_tol + c.rel_tol * asum ? 1 : 0;
+            }
+        }
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+        if (plan.prod_result.size() <= (size_t)ci || plan.prod_result[ci] < 0) continue;
+        const InstResult& r = results[plan.prod_result[ci]];
+        const uint64_t e = (uint64_t)r.slot[0];
+        V[ci].first_index = e ? (int64_t)(~e & ((1ull << 40) - 1)) : -1;  // key = (probe << 40) | row
+        V[ci].holds = e ? 0 : 1;
+        V[ci].measure = r.sum[0];
+    }
+    sg_status status = SG_OK;
+    for (int i = 0; i < nc; ++i)
+        if (V[i].kind == SG_REQUIRE && V[i].holds == 0) { status = SG_PRE_VIOLATED; break; }
+    if (status == SG_PRE_VIOLATED) {
+        for (int i = 0; i < nc; ++i)
+            if (V[i].kind == SG_ENSURE) V[i].holds = -1;
+    } else {
+        for (int i = 0; i < nc; ++i)
+            if (V[i].kind == SG_ENSURE && V[i].holds == 0) { status = SG_POST_VIOLATED; break; }
+    }
+    return status;
+}
+
+sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+    sg_ctx_s* ctx = P->ctx;
+    if (!P->plan.valid || P->plan.generation != ctx->generation) {
+        sg_status st = build_plan(P, &P->plan);
+        if (st != SG_OK) { P->plan.valid = false; return st; }
+    }
+    Plan& plan = P->plan;
+    const int block = ctx->block, unroll = ctx->unroll;
+    const int64_t tile_elems = (int64_t)block * 4 * unroll;
+    int64_t max_tiles = 1;
+    for (auto& ip : plan.insts) max_tiles = std::max<int64_t>(max_tiles, (ip.n + tile_elems - 1) / tile_elems);
+    int nprod = 0;
+    for (auto& st : plan.steps) nprod += st.kind == Step::PRODUCT;
+    const int64_t nres = (int64_t)plan.insts.size() + nprod;
+    sg_status st = ensure_scratch(ctx, max_tiles, nres);
+    if (st != SG_OK) return st;
+    for (auto* m : plan.mats)
+        if ((st = alloc_output(ctx, m)) != SG_OK) return st;
+    Scratch& S = ctx->scratch;
+
+    std::vector<Timed> timed;
+    auto t_begin = [&](const char* name) {
+        if (!ctx->timing) return;
+        hipEvent_t a = get_event(ctx, timed.size() * 2), b = get_event(ctx, timed.size() * 2 + 1);
+        timed.push_back({name, a, b});
+        (void)hipEventRecord(a, ctx->stream);
+    };
+    auto t_end = [&]() {
+        if (!ctx->timing) return;
+        (void)hipEventRecord(timed.back().b, ctx->stream);
+    };
+
+    plan.prod_result.assign(P->contracts.size(), -1);
+    int next_prod = (int)plan.insts.size();
+    for (auto& step : plan.steps) {
+        if (step.kind == Step::STREAM) {
+            InstPlan& ip = plan.insts[step.inst];
+            const int64_t ntiles = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);
+            StreamArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.total_tiles = ntiles;
+            a.acc = S.acc + (int64_t)ip.result_index * MAX_SLOTS;
+            a.tile_sums = S.tile_sums;
+            a.lookback = S.lookback;
+            a.counters = S.counters;
+            a.results = S.results + ip.result_index;
+            a.ninst = 1;
+            a.epoch = S.epoch;
+            fill_inst(ip, a.inst0, 0, ntiles, 0);
+            std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
+            const int grid = stream_grid(ctx, ntiles, true);
+            t_begin("stream");
+            SG_HIP(ctx, sg_launch_stream(a, unroll, true, grid, block, ctx->stream));
+            t_end();
+            for (auto* o : ip.compacted) o->count_dev = &S.results[ip.result_index].scan_count;
+        } else if (step.kind == Step::GEMM) {
+            sg_node_s* C = step.C;
+            if ((st = alloc_output(ctx, C)) != SG_OK) return st;
+            t_begin("gemm");
+            SG_HIP(ctx, sg_launch_gemm_f32((const float*)step.A->dev, (const float*)step.B->dev, (float*)C->dev,
+                                           step.A->rows, step.B->cols, step.A->cols, ctx->stream));
+            t_end();
+            C->count = C->n;
+        } else {
+            const int ri = next_prod++;
+            plan.prod_result[step.contract] = ri;
+            const int64_t M = step.A->rows, K = step.A->cols, N = step.B->cols, nvec = step.R->rows;
+            if (step.C->rows != M || step.C->cols != N || step.B->rows != K || step.R->cols != N)
+                return fail(ctx, SG_E_SHAPE, "product check: dimensions disagree");
+            const double u = std::ldexp(1.0, -24);
+            const double t = 2.0 * (double)K * u;
+            const double tol = t / (1.0 - t) + std::ldexp(1.0, -40);
+            if (nvec < 1 || nvec > 4) return fail(ctx, SG_E_UNSUPPORTED, "product check: 1 to 4 probe vectors");
+            void* work = dev_alloc(ctx, (size_t)(K + M) * 8 * sizeof(double));
+            if (!work) return fail(ctx, SG_E_OOM, "product check workspace");
+            t_begin("product_check");
+            hipError_t e = sg_launch_product_check((const float*)step.C->dev, (const float*)step.A->dev,
+                                                   (const float*)step.B->dev, (const float*)step.R->dev, M, N, K,
+                                                   nvec, tol, (double*)work, S.results + ri, ctx->stream);
+            t_end();
+            dev_free(ctx, work);
+            if (e != hipSuccess) return hip_fail(ctx, e, "product check");
+        }
+    }
+    SG_HIP(ctx, hipMemcpyAsync(ctx->host_results, S.results, (size_t)nres * sizeof(InstResult),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto& t : timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            ctx->times[t.name].ms += ms;
+            ctx->times[t.name].n += 1;
+        }
+    }
+    for (int64_t i = 0; i < nres; ++i) {
+        if (ctx->host_results[i].err) {
+            // reset the state the kernels keep between launches, then report
+            (void)hipMemsetAsync(S.base, 0, S.bytes, ctx->stream);
+            (void)hipStreamSynchronize(ctx->stream);
+            return fail(ctx, SG_E_DEVICE, "streaming kernel reported a device-side failure (look-back timeout)");
+        }
+    }
+
+    const int nc = (int)P->contracts.size();
+    std::vector<sg_verdict> V;
+    sg_status status = assemble_verdicts(P, ctx->host_results, V);
+    const bool publish = status != SG_PRE_VIOLATED;
+    for (auto& ip : plan.insts) publish_inst(ip, ctx->host_results[ip.result_index], publish);
+    for (auto& step : plan.steps)
+        if (step.kind == Step::GEMM) step.C->state = publish ? ST_COMPUTED : ST_UNPUBLISHED;
+    if (nverdicts) *nverdicts = nc;
+    if (verdicts)
+        for (int i = 0; i < nc && i < cap; ++i) verdicts[i] = V[i];
+    return status;
+}
+
+}  // namespace sgrt
+
+using namespace sgrt;
+
+// =============================================================================================
+// C ABI: programs, triggers, results
+// =============================================================================================
+
+extern "C" {
+
+sg_status sg_program_create(sg_ctx ctx, sg_program* out) {
+    if (!ctx || !out) return fail(ctx, SG_E_INVALID, "program_create: NULL argument");
+    auto* p = new sg_program_s();
+    p->ctx = ctx;
+    *out = p;
+    return SG_OK;
+}
+
+sg_status sg_program_add_root(sg_program p, sg_node n) {
+    if (!p || !n) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "add_root: NULL argument");
+    if (n->ctx != p->ctx) return fail(p->ctx, SG_E_INVALID, "add_root: node of another context");
+    retain(n);
+    p->roots.push_back(n);
+    p->plan.valid = false;
+    return SG_OK;
+}
+
+static sg_status add_contract(sg_program p, sgrt::Contract c, int32_t* id) {
+    if (c.kind != SG_REQUIRE && c.kind != SG_ENSURE) return fail(p->ctx, SG_E_INVALID, "contract kind must be require or ensure");
+    c.id = p->next_contract++;
+    for (auto* n : {c.node, c.a, c.b, c.r}) retain(n);
+    retain(c.pred);
+    p->contracts.push_back(c);
+    p->plan.valid = false;
+    if (id) *id = c.id;
+    return SG_OK;
+}
+
+sg_status sg_program_quant(sg_program p, sg_clause kind, sg_quant q, sg_node n, sg_pred pred, int32_t* id) {
+    if (!p || !n || !pred) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "quant: NULL argument");
+    if (!is_collection(n)) return fail(p->ctx, SG_E_INVALID, "quant: operand is a scalar");
+    sgrt::Contract c;
+    c.kind = kind;
+    c.check = q == SG_EXISTS ? SG_CHECK_EXISTS : SG_CHECK_FOR_ALL;
+    c.node = n;
+    c.pred = pred;
+    return add_contract(p, c, id);
+}
+
+sg_status sg_program_sorted(sg_program p, sg_clause kind, sg_node n, int32_t* id) {
+    if (!p || !n) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "sorted: NULL argument");
+    if (!is_collection(n)) return fail(p->ctx, SG_E_INVALID, "sorted: operand is a scalar");
+    sgrt::Contract c;
+    c.kind = kind;
+    c.check = SG_CHECK_SORTED;
+    c.node = n;
+    return add_contract(p, c, id);
+}
+
+sg_status sg_program_close(sg_program p, sg_clause kind, sg_node s, double abs_tol, double rel_tol, int32_t* id) {
+    if (!p || !s) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "close: NULL argument");
+    if (s->op != OPN_REDUCE || s->red != SG_SUM || s->src[0]->dtype != SG_F32)
+        return fail(p->ctx, SG_E_INVALID, "close: operand must be a float sum");
+    if (!(abs_tol >= 0) || !(rel_tol >= 0)) return fail(p->ctx, SG_E_INVALID, "close: tolerances must be >= 0");
+    sgrt::Contract c;
+    c.kind = kind;
+    c.check = SG_CHECK_CLOSE;
+    c.node = s;
+    c.abs_tol = abs_tol;
+    c.rel_tol = rel_tol;
+    return add_contract(p, c, id);
+}
+
+sg_status sg_program_product(sg_program p, sg_clause kind, sg_node C, sg_node A, sg_node B, sg_node R, int32_t* id) {
+    if (!p || !C || !A || !B || !R) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "product: NULL argument");
+    if (!A->matrix || !B->matrix || !C->matrix || !R->matrix) return fail(p->ctx, SG_E_SHAPE, "product: operands must be matrices");
+    if (A->cols != B->rows || C->rows != A->rows || C->cols != B->cols || R->cols != B->cols)
+        return fail(p->ctx, SG_E_SHAPE, "product: dimensions disagree");
+    for (auto* n : {A, B, C, R})
+        if (n->dtype != SG_F32) return fail(p->ctx, SG_E_DTYPE, "product: f32 matrices only");
+    sgrt::Contract c;
+    c.kind = kind;
+    c.check = SG_CHECK_PRODUCT;
+    c.node = C;
+    c.a = A;
+    c.b = B;
+    c.r = R;
+    return add_contract(p, c, id);
+}
+
+sg_status sg_program_split(sg_program p, sg_node n) {
+    if (!p || !n) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "split: NULL argument");
+    retain(n);
+    p->splits.push_back(n);
+    p->plan.valid = false;
+    return SG_OK;
+}
+
+sg_status sg_program_execute(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+    if (!p) return fail(nullptr, SG_E_INVALID, "execute: NULL program");
+    if (cap < 0 || (cap > 0 && !verdicts)) return fail(p->ctx, SG_E_INVALID, "execute: bad verdict buffer");
+    return execute_program(p, verdicts, cap, nverdicts);
+}
+
+sg_status sg_program_release(sg_program p) {
+    if (!p) return SG_E_INVALID;
+    if (--p->refs > 0) return SG_OK;
+    for (auto* r : p->roots) release(r);
+    for (auto& c : p->contracts) {
+        for (auto* n : {c.node, c.a, c.b, c.r}) release(n);
+        release(c.pred);
+    }
+    for (auto* s : p->splits) release(s);
+    delete p;
+    return SG_OK;
+}
+
+sg_status sg_execute(sg_ctx ctx, const sg_node* roots, int32_t nroots) {
+    if (!ctx || nroots < 0 || (nroots > 0 && !roots)) return fail(ctx, SG_E_INVALID, "execute: bad roots");
+    sg_program p;
+    sg_status st = sg_program_create(ctx, &p);
+    if (st != SG_OK) return st;
+    for (int i = 0; i < nroots; ++i)
+        if ((st = sg_program_add_root(p, roots[i])) != SG_OK) { sg_program_release(p); return st; }
+    st = execute_program(p, nullptr, 0, nullptr);
+    sg_program_release(p);
+    return st;
+}
+
+static sg_status trigger(sg_node n) {
+    if (n->state == ST_COMPUTED) return SG_OK;
+    if (n->state == ST_UNPUBLISHED) return fail(n->ctx, SG_E_STATE, "value not published: a require clause failed");
+    sg_node_s* r = n;
+    return sg_execute(n->ctx, &r, 1);
+}
+
+sg_status sg_scalar_get(sg_node s, double* f, int64_t* i) {
+    if (!s) return fail(nullptr, SG_E_INVALID, "scalar_get: NULL node");
+    if (s->op != OPN_REDUCE) return fail(s->ctx, SG_E_INVALID, "scalar_get: not a scalar node");
+    sg_status st = trigger(s);
+    if (st != SG_OK) return st;
+    if (f) *f = s->fval;
+    if (i) *i = s->ival;
+    return SG_OK;
+}
+
+sg_status sg_scalar_shadow(sg_node s, double* f64) {
+    if (!s || !f64) return fail(s ? s->ctx : nullptr, SG_E_INVALID, "scalar_shadow: NULL argument");
+    if (s->op != OPN_REDUCE) return fail(s->ctx, SG_E_INVALID, "scalar_shadow: not a scalar node");
+    sg_status st = trigger(s);
+    if (st != SG_OK) return st;
+    *f64 = s->f64;
+    return SG_OK;
+}
+
+sg_status sg_count(sg_node c, int64_t* n) {
+    if (!c || !n) return fail(c ? c->ctx : nullptr, SG_E_INVALID, "count: NULL argument");
+    if (!is_collection(c)) return fail(c->ctx, SG_E_INVALID, "count: not a collection");
+    sg_status st = trigger(c);
+    if (st != SG_OK) return st;
+    *n = c->count;
+    return SG_OK;
+}
+
+sg_status sg_to_host(sg_node c, void* dst, int64_t cap, int64_t* n) {
+    if (!c || cap < 0 || (cap > 0 && !dst)) return fail(c ? c->ctx : nullptr, SG_E_INVALID, "to_host: bad argument");
+    if (!is_collection(c)) return fail(c->ctx, SG_E_INVALID, "to_host: not a collection");
+    sg_status st = trigger(c);
+    if (st != SG_OK) return st;
+    if (!c->dev && c->count > 0) return fail(c->ctx, SG_E_STATE, "to_host: collection has no storage");
+    const int64_t m = std::min(cap, c->count);
+    if (m > 0) {
+        SG_HIP(c->ctx, hipMemcpyAsync(dst, c->dev, (size_t)m * 4, hipMemcpyDeviceToHost, c->ctx->stream));
+        SG_HIP(c->ctx, hipStreamSynchronize(c->ctx->stream));
+    }
+    if (n) *n = c->count;
+    return SG_OK;
+}
+
+sg_status sg_device_ptr(sg_node c, void** dev, int64_t* n) {
+    if (!c || !dev) return fail(c ? c->ctx : nullptr, SG_E_INVALID, "device_ptr: NULL argument");
+    if (!is_collection(c)) return fail(c->ctx, SG_E_INVALID, "device_ptr: not a collection");
+    sg_status st = trigger(c);
+    if (st != SG_OK) return st;
+    *dev = c->dev;
+    if (n) *n = c->count;
+    return SG_OK;
+}
+
+}  // extern "C"

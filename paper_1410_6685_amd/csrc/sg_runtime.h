@@ -1,0 +1,199 @@
+// Host-side objects of the runtime: context, nodes, agents, programs and plans.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/safegpu.h"
+#include "sg_kernels.h"
+
+namespace sgrt {
+
+enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL };
+enum NodeState { ST_NONE = 0, ST_COMPUTED = 1, ST_UNPUBLISHED = 2 };
+enum FnKind { FK_AFFINE = 0, FK_ADDC, FK_MULC, FK_UNARY, FK_COMPOSE };
+enum PredKind { PK_CMP = 0, PK_FINITE, PK_RANGE, PK_TRUE, PK_AND, PK_OR, PK_NOT };
+
+struct Scratch {
+    void* base = nullptr;
+    uint64_t* acc = nullptr;
+    sg::InstResult* results = nullptr;
+    uint32_t* counters = nullptr;   // [0] ticket, [1] blocks done, [2 + i] tiles done of instance i
+    uint32_t* epoch = nullptr;      // look-back epoch word
+    double* tile_sums = nullptr;
+    uint64_t* lookback = nullptr;
+    int64_t tiles = 0, insts = 0;
+    size_t bytes = 0;
+};
+
+struct KTime { double ms = 0; int64_t n = 0; };
+
+struct Plan;
+
+}  // namespace sgrt
+
+struct sg_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    sg_mode mode = SG_MODE_PRE_POST;
+    bool fused = true;
+    int block = 256;
+    int unroll = 2;
+    bool timing = false;
+    uint64_t next_id = 0;
+    uint64_t generation = 0;  // bumped when a setting that changes plans changes
+    std::string error;
+    std::map<size_t, std::vector<void*>> pool;
+    std::unordered_map<void*, size_t> sizes;
+    sgrt::Scratch scratch;
+    sg::InstResult* host_results = nullptr;
+    std::map<std::string, sgrt::KTime> times;
+    std::vector<hipEvent_t> events;
+    std::map<std::pair<int, int>, int> occupancy;  // (unroll, block) -> blocks per CU
+};
+
+struct sg_fn_s {
+    int refs = 1;
+    int kind = 0;
+    double a = 0, b = 0;
+    sg_fn_s* f = nullptr;
+    sg_fn_s* g = nullptr;
+};
+
+struct sg_pred_s {
+    int refs = 1;
+    int kind = 0;
+    int cmp = 0;
+    double c = 0, lo = 0, hi = 0;
+    sg_pred_s* p = nullptr;
+    sg_pred_s* q = nullptr;
+};
+
+struct sg_node_s {
+    int refs = 1;
+    sg_ctx_s* ctx = nullptr;
+    int op = 0;
+    sg_dtype dtype = SG_F32;
+    int64_t n = 0;  // capacity (element count of the unfiltered index space)
+    bool matrix = false;
+    int64_t rows = 0, cols = 0;
+    sg_node_s* src[2] = {nullptr, nullptr};
+    sg_fn_s* fn = nullptr;
+    sg_pred_s* pred = nullptr;
+    int binop = 0, red = 0;
+    uint64_t space = 0;  // index-space identity (filters start a new one)
+    uint64_t id = 0;     // creation order: a topological order of the DAG
+    // storage of a materialized collection
+    void* dev = nullptr;
+    bool owned = false;
+    size_t bytes = 0;
+    // results
+    int state = sgrt::ST_NONE;
+    int64_t count = 0;     // elements of a computed collection
+    double fval = 0.0;     // scalar value (float results rounded to their dtype)
+    double f64 = 0.0;      // float64 shadow of float sums / averages
+    int64_t ival = 0;      // integer scalar value
+    const int64_t* count_dev = nullptr;  // device address of a compacted collection's count
+};
+
+namespace sgrt {
+
+struct Contract {
+    int32_t id = 0;
+    int kind = SG_REQUIRE;
+    int check = SG_CHECK_FOR_ALL;
+    sg_node_s* node = nullptr;
+    sg_pred_s* pred = nullptr;
+    sg_node_s *a = nullptr, *b = nullptr, *r = nullptr;  // product check operands
+    double abs_tol = 0, rel_tol = 0;
+};
+
+// One pass of the streaming kernel.
+struct InstPlan {
+    std::vector<sg_node_s*> sources;   // loaded into registers 0..nin-1
+    std::vector<sg::SgOp> prog;
+    std::vector<sg_node_s*> outs;      // materialized outputs, out[k]
+    std::vector<uint8_t> slot_kind;
+    int nsum = 0;
+    int scan_space = 0;
+    int count_slot = -1;
+    int base_count_slot = -1;          // count of space 0 when it is a compacted source's
+    int64_t n = 0;                     // element count (capacity when n_src is set)
+    sg_node_s* n_src = nullptr;        // compacted source whose device count is n
+    struct ScalarOut { sg_node_s* node; int slot; int sum; int count_slot; };
+    std::vector<ScalarOut> scalars;
+    struct CheckOut { int contract; int slot; };
+    std::vector<CheckOut> checks;
+    struct AbsSum { int contract; int sum; };
+    std::vector<AbsSum> abssums;
+    std::vector<sg_node_s*> compacted;  // outputs whose count is the scan count
+    int result_index = 0;               // slot in the results array
+};
+
+struct Step {
+    enum Kind { STREAM = 0, GEMM = 1, PRODUCT = 2 } kind = STREAM;
+    int inst = -1;                           // STREAM
+    sg_node_s *A = nullptr, *B = nullptr, *C = nullptr, *R = nullptr;  // GEMM / PRODUCT
+    int contract = -1;                       // PRODUCT
+};
+
+struct Plan {
+    std::vector<InstPlan> insts;
+    std::vector<Step> steps;
+    std::vector<int> active;        // contracts evaluated (indices into the program's list)
+    std::vector<sg_node_s*> mats;   // nodes materialized by this plan
+    std::vector<int> prod_result;   // contract -> result slot of its product check (-1)
+    uint64_t generation = 0;
+    bool valid = false;
+};
+
+sg_status fail(sg_ctx_s* ctx, sg_status st, const std::string& msg);
+sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what);
+void* dev_alloc(sg_ctx_s* ctx, size_t bytes);
+void dev_free(sg_ctx_s* ctx, void* p);
+sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t insts);
+sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t insts);
+void fill_inst(const InstPlan& ip, sg::InstDesc& d, int64_t tile0, int64_t ntiles, int prog_off);
+void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_values);
+sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n);
+sg_status assemble_verdicts(sg_program_s* P, const sg::InstResult* results, std::vector<sg_verdict>& V);
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl);
+void retain(sg_node_s* n);
+void retain(sg_fn_s* f);
+void retain(sg_pred_s* p);
+void release(sg_node_s* n);
+void release(sg_fn_s* f);
+void release(sg_pred_s* p);
+bool is_elementwise(const sg_node_s* n);
+bool is_collection(const sg_node_s* n);
+void emit_fn(std::vector<sg::SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt);
+void emit_pred(std::vector<sg::SgOp>& prog, const sg_pred_s* p, int r, sg_dtype dt);
+
+}  // namespace sgrt
+
+struct sg_program_s {
+    int refs = 1;
+    sg_ctx_s* ctx = nullptr;
+    std::vector<sg_node_s*> roots;
+    std::vector<sgrt::Contract> contracts;
+    std::vector<sg_node_s*> splits;
+    sgrt::Plan plan;
+    int32_t next_contract = 0;
+};
+
+struct sg_batch_s;
+
+#define SG_HIP(ctx, call)                                              \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return sgrt::hip_fail((ctx), _e, #call); \
+    } while (0)
+
+namespace sgrt {
+sg_status build_plan(sg_program_s* P, Plan* out);
+sg_status execute_program(sg_program_s* P, sg_verdict* v, int32_t cap, int32_t* nv);
+}  // namespace sgrt
