@@ -4,7 +4,8 @@
 // Instances are laid out back to back in one tile space; a tile-to-instance table lets every
 // block find its instance with one load.  Each instance keeps its own accumulators, look-back
 // range and finalization, so results equal those of separate launches.  The batch owns its
-// scratch, so the graph's baked addresses stay valid whatever else runs on the context.
+// scratch, so the graph's baked addresses stay valid whatever else runs on the context; the
+// graph is [advance the device epoch word, streaming kernel] and needs no memset nodes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +19,7 @@ using namespace sg;
 using namespace sgrt;
 
 hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
+hipError_t sg_launch_epoch_bump(uint32_t* e, hipStream_t s);
 
 struct sg_batch_s {
     sg_ctx_s* ctx = nullptr;
@@ -25,7 +27,7 @@ struct sg_batch_s {
     Scratch scratch;
     void* table = nullptr;           // InstDesc[] | SgOp[] | int32 tile_inst[]
     StreamArgs args;
-    int grid = 1, block = 256, unroll = 2;
+    int grid = 1, block = 256, unroll = 2, substeps = 1;
     int64_t total_tiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -51,6 +53,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     b->ctx = ctx;
     b->block = ctx->block;
     b->unroll = ctx->unroll;
+    b->substeps = 1;  // one sub-tile per tile: instances are small next to the grid
     const int64_t tile_elems = (int64_t)b->block * 4 * b->unroll;
     std::vector<InstDesc> descs;
     std::vector<SgOp> ops;
@@ -78,7 +81,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
         for (int64_t t = 0; t < nt; ++t) tile_inst.push_back(i);
         b->total_tiles += nt;
     }
-    sg_status st = alloc_scratch(ctx, b->scratch, b->total_tiles, n);
+    sg_status st = alloc_scratch(ctx, b->scratch, b->total_tiles, b->total_tiles * b->substeps * MAX_WAVES, n);
     if (st != SG_OK) { batch_free(b); return st; }
     const size_t db = descs.size() * sizeof(InstDesc), ob = ops.size() * sizeof(SgOp), tb = tile_inst.size() * 4;
     const size_t off_o = (db + 255) & ~(size_t)255, off_t = (off_o + ob + 255) & ~(size_t)255;
@@ -101,12 +104,14 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     a.tile_inst = (const int32_t*)(base + off_t);
     a.total_tiles = b->total_tiles;
     a.acc = b->scratch.acc;
-    a.tile_sums = b->scratch.tile_sums;
+    a.tags = b->scratch.tags;
     a.lookback = b->scratch.lookback;
-    a.counters = b->scratch.counters;
-    a.epoch = b->scratch.epoch;
+    a.epoch_ptr = b->scratch.epoch;
     a.results = b->scratch.results;
     a.ninst = n;
+    a.substeps = b->substeps;
+    a.spread = 1;
+    a.interleave = 1;
     b->grid = stream_grid(ctx, b->total_tiles, false);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "batch sync"); }
     if (use_graph) {
@@ -119,6 +124,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
             own = true;
         }
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = sg_launch_epoch_bump(b->scratch.epoch, cs);
         if (e == hipSuccess) e = sg_launch_stream(a, b->unroll, false, b->grid, b->block, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
         if (own) (void)hipStreamDestroy(cs);
@@ -133,8 +139,12 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
 sg_status sg_batch_launch(sg_batch b) {
     if (!b) return fail(nullptr, SG_E_INVALID, "batch_launch: NULL batch");
     sg_ctx_s* ctx = b->ctx;
-    if (b->exec) SG_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
-    else SG_HIP(ctx, sg_launch_stream(b->args, b->unroll, false, b->grid, b->block, ctx->stream));
+    if (b->exec) {
+        SG_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
+    } else {
+        SG_HIP(ctx, sg_launch_epoch_bump(b->scratch.epoch, ctx->stream));
+        SG_HIP(ctx, sg_launch_stream(b->args, b->unroll, false, b->grid, b->block, ctx->stream));
+    }
     return SG_OK;
 }
 

@@ -235,14 +235,26 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         if (st != SG_OK) { P->plan.valid = false; return st; }
     }
     Plan& plan = P->plan;
-    const int block = ctx->block, unroll = ctx->unroll;
-    const int64_t tile_elems = (int64_t)block * 4 * unroll;
+    const int block = ctx->block, unroll = ctx->unroll, C = ctx->substeps;
+    const int64_t sub_elems = (int64_t)block * 4 * unroll;
+    // grid and tile count of one pass: G blocks, each holding R tiles of C sub-tiles
+    auto geometry = [&](int64_t n, int& grid, int64_t& ntiles) {
+        const int64_t nsub = std::max<int64_t>(1, (n + sub_elems - 1) / sub_elems);
+        grid = stream_grid(ctx, (nsub + C - 1) / C, true);
+        const int64_t R = (nsub + (int64_t)grid * C - 1) / ((int64_t)grid * C);
+        ntiles = R * grid;
+    };
     int64_t max_tiles = 1;
-    for (auto& ip : plan.insts) max_tiles = std::max<int64_t>(max_tiles, (ip.n + tile_elems - 1) / tile_elems);
+    for (auto& ip : plan.insts) {
+        int g;
+        int64_t nt;
+        geometry(ip.n, g, nt);
+        max_tiles = std::max(max_tiles, nt);
+    }
     int nprod = 0;
     for (auto& st : plan.steps) nprod += st.kind == Step::PRODUCT;
     const int64_t nres = (int64_t)plan.insts.size() + nprod;
-    sg_status st = ensure_scratch(ctx, max_tiles, nres);
+    sg_status st = ensure_scratch(ctx, max_tiles, max_tiles * C * MAX_WAVES, nres);
     if (st != SG_OK) return st;
     for (auto* m : plan.mats)
         if ((st = alloc_output(ctx, m)) != SG_OK) return st;
@@ -265,20 +277,23 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     for (auto& step : plan.steps) {
         if (step.kind == Step::STREAM) {
             InstPlan& ip = plan.insts[step.inst];
-            const int64_t ntiles = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);
+            int grid;
+            int64_t ntiles;
+            geometry(ip.n, grid, ntiles);
             StreamArgs a;
             std::memset(&a, 0, sizeof(a));
             a.total_tiles = ntiles;
-            a.acc = S.acc + (int64_t)ip.result_index * MAX_SLOTS;
-            a.tile_sums = S.tile_sums;
+            a.acc = S.acc + (int64_t)ip.result_index * MAX_SLOTS * MAX_SPREAD;
+            a.tags = S.tags;
             a.lookback = S.lookback;
-            a.counters = S.counters;
             a.results = S.results + ip.result_index;
             a.ninst = 1;
-            a.epoch = S.epoch;
+            a.substeps = C;
+            a.spread = MAX_SPREAD;
+            a.interleave = grid;
+            a.epoch_val = next_epoch(ctx);
             fill_inst(ip, a.inst0, 0, ntiles, 0);
             std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
-            const int grid = stream_grid(ctx, ntiles, true);
             t_begin("stream");
             SG_HIP(ctx, sg_launch_stream(a, unroll, true, grid, block, ctx->stream));
             t_end();
@@ -327,7 +342,8 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
             // reset the state the kernels keep between launches, then report
             (void)hipMemsetAsync(S.base, 0, S.bytes, ctx->stream);
             (void)hipStreamSynchronize(ctx->stream);
-            return fail(ctx, SG_E_DEVICE, "streaming kernel reported a device-side failure (look-back timeout)");
+            ctx->epoch = 0;
+            return fail(ctx, SG_E_DEVICE, "streaming kernel reported a device-side failure (a bounded wait timed out)");
         }
     }
 

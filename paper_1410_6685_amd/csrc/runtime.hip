@@ -78,48 +78,61 @@ void dev_free(sg_ctx_s* ctx, void* p) {
     ctx->pool[it->second].push_back(p);
 }
 
-// Scratch of the streaming kernel, zeroed once: the kernels leave it zero (accumulators,
-// counters) or tag it with the device epoch (look-back descriptors).
-sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t insts) {
+// Scratch of the streaming kernel, zeroed once: the kernel leaves the accumulators zero and
+// tags everything else with the launch epoch.
+sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t chunks, int64_t insts) {
     if (S.base) (void)hipFree(S.base);
     S = Scratch();
-    const int64_t nt = std::max<int64_t>(tiles, 1), ni = std::max<int64_t>(insts, 1);
-    // layout (bytes): acc | results | counters + epoch | tile_sums | lookback
-    size_t acc_b = (size_t)ni * MAX_SLOTS * 8;
+    const int64_t nt = std::max<int64_t>(tiles, 1), nc = std::max<int64_t>(chunks, 1), ni = std::max<int64_t>(insts, 1);
+    // layout (bytes): acc | results | tags | lookback | epoch
+    size_t acc_b = (size_t)ni * MAX_SLOTS * MAX_SPREAD * 8;
     size_t res_b = (size_t)ni * sizeof(InstResult);
-    size_t cnt_b = ((size_t)(3 + ni) * 4 + 255) & ~(size_t)255;
-    size_t ts_b = (size_t)nt * MAX_SUMS * 8;
-    size_t lb_b = (size_t)nt * 8;
-    size_t total = acc_b + res_b + cnt_b + ts_b + lb_b;
+    size_t tag_b = (size_t)nt * TAG_WORDS * 8;
+    size_t lb_b = (size_t)nc * 8;
+    size_t ep_b = 256;
+    size_t total = acc_b + res_b + tag_b + lb_b + ep_b;
     void* p = nullptr;
     SG_HIP(ctx, hipMalloc(&p, total));
     S.base = p;
     char* c = (char*)p;
     S.acc = (uint64_t*)c; c += acc_b;
     S.results = (InstResult*)c; c += res_b;
-    S.counters = (uint32_t*)c;
-    S.epoch = S.counters + 2 + ni;
-    c += cnt_b;
-    S.tile_sums = (double*)c; c += ts_b;
-    S.lookback = (uint64_t*)c;
+    S.tags = (uint64_t*)c; c += tag_b;
+    S.lookback = (uint64_t*)c; c += lb_b;
+    S.epoch = (uint32_t*)c;
     S.tiles = nt;
+    S.chunks = nc;
     S.insts = ni;
     S.bytes = total;
     SG_HIP(ctx, sg_launch_zero((uint64_t*)p, (int64_t)(total / 8), ctx->stream));
     return SG_OK;
 }
 
-sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t insts) {
+sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t chunks, int64_t insts) {
     Scratch& S = ctx->scratch;
-    if (tiles <= S.tiles && insts <= S.insts) return SG_OK;
+    if (tiles <= S.tiles && chunks <= S.chunks && insts <= S.insts) return SG_OK;
     SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    sg_status st = alloc_scratch(ctx, S, std::max<int64_t>({tiles, S.tiles * 2, 4096}),
-                                 std::max<int64_t>({insts, S.insts * 2, 64}));
+    sg_status st = alloc_scratch(ctx, S, std::max<int64_t>({tiles, S.tiles * 2, 1024}),
+                                 std::max<int64_t>({chunks, S.chunks * 2, 16384}),
+                                 std::max<int64_t>({insts, S.insts * 2, 16}));
     if (st != SG_OK) return st;
+    ctx->epoch = 0;
     if (ctx->host_results) (void)hipHostFree(ctx->host_results);
     ctx->host_results = nullptr;
     SG_HIP(ctx, hipHostMalloc((void**)&ctx->host_results, (size_t)S.insts * sizeof(InstResult), hipHostMallocDefault));
     return SG_OK;
+}
+
+// Epoch of the next direct launch.  Look-back descriptors keep 30 bits of it: on wrap-around
+// they are cleared so that no descriptor of an earlier launch can look current.
+uint32_t next_epoch(sg_ctx_s* ctx) {
+    ctx->epoch = (ctx->epoch + 1) & 0x3FFFFFFFu;
+    if (ctx->epoch == 0) {
+        (void)sg_launch_zero(ctx->scratch.lookback, ctx->scratch.chunks, ctx->stream);
+        (void)sg_launch_zero(ctx->scratch.tags, ctx->scratch.tiles * TAG_WORDS, ctx->stream);
+        ctx->epoch = 1;
+    }
+    return ctx->epoch;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -25,6 +25,9 @@ constexpr int MAX_DEFER = 2;       // contracts on the scan space (need compacte
 constexpr int MAX_CEMIT = 2;       // compacted outputs per instance
 constexpr int MAX_INLINE_OPS = 48; // program length of a single-instance launch
 constexpr int MAX_WAVES = 16;      // 1024 threads per block
+constexpr int TAG_WORDS = 1 + 2 * MAX_SUMS;  // per tile: done word, then each float64 sum as two halves
+constexpr int MAX_SPREAD = 64;
+constexpr int TILE_BUF = 32;       // tiles a block holds before publishing them
 
 enum OpCode : uint8_t {
     OP_NOP = 0,
@@ -97,23 +100,23 @@ struct InstResult {
 };
 static_assert(sizeof(InstResult) == 256, "result size");
 
-enum ErrBits : uint32_t { ERR_LOOKBACK_TIMEOUT = 1u, ERR_BAD_OP = 2u };
+enum ErrBits : uint32_t { ERR_LOOKBACK_TIMEOUT = 1u, ERR_FINALIZE_TIMEOUT = 2u };
 
 struct StreamArgs {
     const InstDesc* insts;      // batched launches: instance table (device)
     const SgOp* progs;          // batched launches: programs (device)
-    const int64_t* tile_prefix; // batched launches: first tile of each instance, ninst+1
-    int64_t total_tiles;
-    uint64_t* acc;              // ninst x MAX_SLOTS accumulators (zero between launches)
-    double* tile_sums;          // total_tiles x MAX_SUMS partial sums
-    uint64_t* lookback;         // total_tiles compaction descriptors
-    uint32_t* counters;         // [0] tile ticket, [1] blocks done, [2 + i] tiles done of instance i
     const int32_t* tile_inst;   // batched launches: instance of every tile
+    int64_t total_tiles;
+    uint64_t* acc;              // ninst x MAX_SLOTS x spread accumulators (zero between launches)
+    uint64_t* tags;             // total_tiles x TAG_WORDS epoch-tagged per-tile words
+    uint64_t* lookback;         // total_tiles x substeps x waves compaction descriptors
     InstResult* results;        // ninst
-    uint32_t* epoch;            // device word tagging this launch's look-back descriptors;
-                                // the last block to finish advances it
+    const uint32_t* epoch_ptr;  // graph replays: device word advanced before every launch
+    uint32_t epoch_val;         // direct launches: this launch's epoch
     int32_t ninst;
-    int32_t pad;
+    int32_t substeps;           // sub-steps of blockDim.x * 4U elements per tile
+    int32_t spread;             // accumulator copies per slot (spreads same-address atomics)
+    int32_t interleave;         // sub-step c of local tile l covers sub-tile ((l/I)*C + c)*I + l%I
     InstDesc inst0;             // single-instance launches: the instance
     SgOp prog0[MAX_INLINE_OPS]; // single-instance launches: its program
 };

@@ -19,13 +19,12 @@ enum PredKind { PK_CMP = 0, PK_FINITE, PK_RANGE, PK_TRUE, PK_AND, PK_OR, PK_NOT 
 
 struct Scratch {
     void* base = nullptr;
-    uint64_t* acc = nullptr;
+    uint64_t* acc = nullptr;          // insts x MAX_SLOTS x MAX_SPREAD
     sg::InstResult* results = nullptr;
-    uint32_t* counters = nullptr;   // [0] ticket, [1] blocks done, [2 + i] tiles done of instance i
-    uint32_t* epoch = nullptr;      // look-back epoch word
-    double* tile_sums = nullptr;
-    uint64_t* lookback = nullptr;
-    int64_t tiles = 0, insts = 0;
+    uint64_t* tags = nullptr;         // tiles x TAG_WORDS
+    uint64_t* lookback = nullptr;     // tiles x substeps x MAX_WAVES
+    uint32_t* epoch = nullptr;        // device epoch word (graph replays)
+    int64_t tiles = 0, insts = 0, chunks = 0;
     size_t bytes = 0;
 };
 
@@ -43,6 +42,8 @@ struct sg_ctx_s {
     bool fused = true;
     int block = 256;
     int unroll = 2;
+    int substeps = 8;
+    uint32_t epoch = 0;  // host epoch of direct launches
     bool timing = false;
     uint64_t next_id = 0;
     uint64_t generation = 0;  // bumped when a setting that changes plans changes
@@ -155,8 +156,9 @@ sg_status fail(sg_ctx_s* ctx, sg_status st, const std::string& msg);
 sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what);
 void* dev_alloc(sg_ctx_s* ctx, size_t bytes);
 void dev_free(sg_ctx_s* ctx, void* p);
-sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t insts);
-sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t insts);
+sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t chunks, int64_t insts);
+sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t chunks, int64_t insts);
+uint32_t next_epoch(sg_ctx_s* ctx);
 void fill_inst(const InstPlan& ip, sg::InstDesc& d, int64_t tile0, int64_t ntiles, int prog_off);
 void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_values);
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n);
