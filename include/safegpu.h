@@ -203,6 +203,57 @@ sg_status sg_batch_run(sg_batch b, int32_t* status_out, sg_verdict* verdicts, in
 sg_status sg_batch_launch(sg_batch b);
 sg_status sg_batch_release(sg_batch b);
 
+/* ---- plans: autotuner and learned selector ------------------------------------------------ */
+
+/* A launch plan of a program's streaming passes: block size (64..1024, multiple of 64),
+ * 16-byte loads per lane and input (1, 2 or 4), sub-tiles per tile (1..64), and an optional
+ * fusion split point (index into the program's split candidates -- its map/zip/filter nodes
+ * in creation order -- or -1): the node is then materialized and its consumers start a new
+ * pass. */
+typedef struct sg_plan { int32_t block, unroll, substeps, split; } sg_plan;
+
+typedef struct sg_mlp_s* sg_mlp;
+
+sg_status sg_program_split_candidates(sg_program p, int32_t* n);
+/* NULL restores the context defaults. */
+sg_status sg_program_set_plan(sg_program p, const sg_plan* plan);
+/* Cost-model features of (program, plan), 24 floats:
+ *  0 affine/add_c/mul_c maps, 1 sqrt maps, 2 exp maps, 3 other unary maps, 4 zip add/sub,
+ *  5 zip mul, 6 filters, 7 sums/averages, 8 min/max, 9 counts, 10 for_all/exists clauses,
+ *  11 other clauses, 12 depth, 13 log2 length, 14 float32 data, 15 input collections,
+ *  16 log2 block, 17 log2 unroll, 18 log2 sub-steps, 19 has split, 20 split position,
+ *  21 passes, 22 bytes moved per element, 23 resident blocks per CU. */
+sg_status sg_program_features(sg_program p, const sg_plan* plan, float* f24);
+/* Autotuner: device time in ms (median of reps runs after one warm-up) of every plan. */
+sg_status sg_program_time_plans(sg_program p, const sg_plan* plans, int32_t n, int32_t reps, double* ms_out);
+/* Time every plan, set the fastest on the program; *best its index, ms_out (n) the timings. */
+sg_status sg_autotune(sg_program p, const sg_plan* plans, int32_t n, int32_t reps, int32_t* best, double* ms_out);
+
+/* The cost model: a 24-64-64-1 float32 MLP with ReLU predicting log run time (us) from
+ * standardized features.  Parameters (5825 floats): W1[24][64] b1[64] W2[64][64] b2[64]
+ * W3[64] b3, initial values supplied by the caller. */
+sg_status sg_mlp_create(sg_ctx ctx, const float* params, int64_t nparams, sg_mlp* out);
+sg_status sg_mlp_release(sg_mlp m);
+sg_status sg_mlp_get_params(sg_mlp m, float* params, int64_t nparams);
+/* Loss (mean squared error) and gradient of one batch of B <= 128 samples (device X B x 24,
+ * device targets T B) without updating: grad_host receives 5825 floats. */
+sg_status sg_mlp_grad(sg_mlp m, const float* X_dev, const float* T_dev, int32_t B, float* grad_host, double* loss);
+/* Adam training (beta 0.9/0.999, eps 1e-8) over n device samples in the given order, in
+ * batches of `batch` <= 128, for `epochs` epochs; epoch_loss (host, epochs doubles) gets
+ * each epoch's mean loss. */
+sg_status sg_mlp_train(sg_mlp m, const float* X_dev, const float* T_dev, int64_t n, int32_t batch, int32_t epochs,
+                       float lr, double* epoch_loss);
+/* Predictions for n device samples (X n x 24) into device Y (n). */
+sg_status sg_mlp_predict(sg_mlp m, const float* X_dev, int64_t n, float* Y_dev);
+/* Standardization x' = (x - mean) / scale and the training range [lo, hi] of each feature. */
+sg_status sg_mlp_set_norm(sg_mlp m, const float* mean24, const float* scale24, const float* lo24, const float* hi24);
+/* Learned selector: predict all candidates, set the argmin on the program unless a feature
+ * is out of the training range or the best two predictions are closer than `margin` (log
+ * units), in which case *fallback = 1 and the program's plan is unchanged (the caller runs
+ * the autotuner).  pred_out (n, optional) receives the predictions. */
+sg_status sg_select_plan(sg_mlp m, sg_program p, const sg_plan* plans, int32_t n, float margin, int32_t* best,
+                         float* pred_out, int32_t* fallback);
+
 /* ---- host-side checks of device arithmetic (no GPU needed) ------------------------------ */
 
 /* Evaluate the device code's correctly rounded binary32 exp on the host for n values;

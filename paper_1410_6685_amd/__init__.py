@@ -30,6 +30,24 @@ CLAUSE = {"require": 0, "ensure": 1}
 CHECKS = {0: "for_all", 1: "exists", 2: "sorted", 3: "close", 4: "product"}
 
 
+class Plan(ctypes.Structure):
+    """Launch plan of a program: block, unroll, sub-steps per tile, fusion split (-1 none)."""
+    _fields_ = [("block", c_int32), ("unroll", c_int32), ("substeps", c_int32), ("split", c_int32)]
+
+    def as_tuple(self):
+        return (self.block, self.unroll, self.substeps, self.split)
+
+    def __repr__(self):
+        return f"Plan{self.as_tuple()}"
+
+
+def plans_array(plans):
+    arr = (Plan * len(plans))()
+    for i, p in enumerate(plans):
+        arr[i] = p if isinstance(p, Plan) else Plan(*p)
+    return arr
+
+
 class Verdict(ctypes.Structure):
     _fields_ = [("contract_id", c_int32), ("kind", c_int32), ("holds", c_int32), ("check", c_int32),
                 ("first_index", c_int64), ("measure", c_double)]
@@ -78,6 +96,15 @@ def _sig(lib):
         "sg_batch_run": [H, P(c_int32), P(Verdict), c_int32, P(c_int32)],
         "sg_batch_launch": [H], "sg_batch_release": [H],
         "sg_host_exp_rn": [H, H, c_int64, P(c_int64)],
+        "sg_program_split_candidates": [H, P(c_int32)], "sg_program_set_plan": [H, H],
+        "sg_program_features": [H, H, P(ctypes.c_float)],
+        "sg_program_time_plans": [H, H, c_int32, c_int32, P(c_double)],
+        "sg_autotune": [H, H, c_int32, c_int32, P(c_int32), P(c_double)],
+        "sg_mlp_create": [H, H, c_int64, P(H)], "sg_mlp_release": [H], "sg_mlp_get_params": [H, H, c_int64],
+        "sg_mlp_grad": [H, H, H, c_int32, H, P(c_double)],
+        "sg_mlp_train": [H, H, H, c_int64, c_int32, c_int32, ctypes.c_float, P(c_double)],
+        "sg_mlp_predict": [H, H, c_int64, H], "sg_mlp_set_norm": [H, H, H, H, H],
+        "sg_select_plan": [H, H, H, c_int32, ctypes.c_float, P(c_int32), H, P(c_int32)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -331,6 +358,37 @@ class Program:
         _check(load().sg_program_split(self.h, n.h), self.ctx.h)
         self._keep.append(n)
 
+    def split_candidates(self) -> int:
+        n = c_int32()
+        _check(load().sg_program_split_candidates(self.h, byref(n)), self.ctx.h)
+        return n.value
+
+    def set_plan(self, plan=None):
+        if plan is None:
+            _check(load().sg_program_set_plan(self.h, None), self.ctx.h)
+        else:
+            p = plan if isinstance(plan, Plan) else Plan(*plan)
+            _check(load().sg_program_set_plan(self.h, byref(p)), self.ctx.h)
+
+    def features(self, plan):
+        p = plan if isinstance(plan, Plan) else Plan(*plan)
+        out = (ctypes.c_float * 24)()
+        _check(load().sg_program_features(self.h, byref(p), out), self.ctx.h)
+        return list(out)
+
+    def time_plans(self, plans, reps: int = 3):
+        arr = plans_array(plans)
+        ms = (c_double * len(plans))()
+        _check(load().sg_program_time_plans(self.h, arr, len(plans), reps, ms), self.ctx.h)
+        return list(ms)
+
+    def autotune(self, plans, reps: int = 3):
+        arr = plans_array(plans)
+        ms = (c_double * len(plans))()
+        best = c_int32()
+        _check(load().sg_autotune(self.h, arr, len(plans), reps, byref(best), ms), self.ctx.h)
+        return best.value, list(ms)
+
     def execute(self, cap: int = 64):
         """Run the program.  Returns (status name, [Verdict...]); raises on API errors."""
         buf = (Verdict * cap)()
@@ -338,6 +396,67 @@ class Program:
         st = load().sg_program_execute(self.h, buf, cap, byref(nv))
         _check(st, self.ctx.h, ok=(0, 16, 17))
         return STATUS[st], [buf[i] for i in range(min(nv.value, cap))]
+
+
+class Mlp:
+    """The 24-64-64-1 cost model (parameters in the C ABI's layout, 5825 floats)."""
+    NPARAMS = 5825
+
+    def __init__(self, ctx: "Context", params):
+        import numpy as np
+        self.ctx = ctx
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.h = c_void_p()
+        _check(load().sg_mlp_create(ctx.h, p.ctypes.data, p.size, byref(self.h)), ctx.h)
+
+    def __del__(self):
+        if self.h and _lib is not None:
+            _lib.sg_mlp_release(self.h)
+            self.h = None
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.NPARAMS, np.float32)
+        _check(load().sg_mlp_get_params(self.h, out.ctypes.data, out.size), self.ctx.h)
+        return out
+
+    def grad(self, X, T):
+        """X, T: CUDA float32 tensors (B x 24, B).  Returns (loss, gradient as numpy)."""
+        import numpy as np
+        g = np.empty(self.NPARAMS, np.float32)
+        loss = c_double()
+        _check(load().sg_mlp_grad(self.h, c_void_p(X.data_ptr()), c_void_p(T.data_ptr()), X.shape[0],
+                                  g.ctypes.data, byref(loss)), self.ctx.h)
+        return loss.value, g
+
+    def train(self, X, T, batch: int = 128, epochs: int = 10, lr: float = 1e-3):
+        import numpy as np
+        el = np.empty(epochs, np.float64)
+        _check(load().sg_mlp_train(self.h, c_void_p(X.data_ptr()), c_void_p(T.data_ptr()), X.shape[0], batch,
+                                   epochs, lr, el.ctypes.data_as(POINTER(c_double))), self.ctx.h)
+        return el
+
+    def predict(self, X):
+        import torch
+        Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(load().sg_mlp_predict(self.h, c_void_p(X.data_ptr()), X.shape[0], c_void_p(Y.data_ptr())), self.ctx.h)
+        torch.cuda.synchronize()
+        return Y
+
+    def set_norm(self, mean, scale, lo, hi):
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (mean, scale, lo, hi)]
+        _check(load().sg_mlp_set_norm(self.h, *[a.ctypes.data for a in arrs]), self.ctx.h)
+
+    def select(self, program: "Program", plans, margin: float = 0.01):
+        """Learned plan choice: (best index, predictions, fallback flag)."""
+        import numpy as np
+        arr = plans_array(plans)
+        pred = np.empty(len(plans), np.float32)
+        best, fb = c_int32(), c_int32()
+        _check(load().sg_select_plan(self.h, program.h, arr, len(plans), margin, byref(best), pred.ctypes.data,
+                                     byref(fb)), self.ctx.h)
+        return best.value, pred, bool(fb.value)
 
 
 class Batch:

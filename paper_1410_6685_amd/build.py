@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libsafegpu.so")
-SOURCES = ["stream.hip", "gemm.hip", "product.hip", "runtime.hip", "planner.hip", "exec.hip", "batch.hip",
+SOURCES = ["stream.hip", "gemm.hip", "product.hip", "runtime.hip", "planner.hip", "exec.hip", "batch.hip", "mlp.hip", "tune.hip",
            "host_checks.hip"]
 ARCH = os.environ.get("SG_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",

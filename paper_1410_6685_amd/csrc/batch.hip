@@ -72,7 +72,6 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
             if ((st = alloc_output(ctx, m)) != SG_OK) { batch_free(b); return st; }
         InstPlan& ip = plan.insts[0];
         if (ip.n_src) { batch_free(b); return fail(ctx, SG_E_UNSUPPORTED, "batch: sources must have host-known lengths"); }
-        ip.result_index = i;
         const int64_t nt = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);
         InstDesc d;
         fill_inst(ip, d, b->total_tiles, nt, (int)ops.size());
@@ -112,7 +111,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     a.substeps = b->substeps;
     a.spread = 1;
     a.interleave = 1;
-    b->grid = stream_grid(ctx, b->total_tiles, false);
+    b->grid = stream_grid(ctx, b->total_tiles, false, b->unroll, b->block);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "batch sync"); }
     if (use_graph) {
         // the graph holds only the kernel node (no memset nodes): the kernel leaves its
@@ -165,11 +164,9 @@ sg_status sg_batch_run(sg_batch b, int32_t* status_out, sg_verdict* verdicts, in
     std::vector<InstResult> one(1);
     for (int i = 0; i < n; ++i) {
         sg_program_s* P = b->progs[i];
-        one[0] = b->host[i];
-        P->plan.insts[0].result_index = 0;
+        one[0] = b->host[i];  // the program's own plan reads its pass from result 0
         sg_status ps = assemble_verdicts(P, one.data(), V);
         publish_inst(P->plan.insts[0], one[0], ps != SG_PRE_VIOLATED);
-        P->plan.insts[0].result_index = i;
         if (status_out) status_out[i] = ps;
         for (auto& v : V) {
             if (nv < cap) verdicts[nv] = v;

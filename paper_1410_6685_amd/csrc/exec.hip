@@ -54,14 +54,14 @@ float key_to_float(int32_t k) {
 
 }  // namespace
 
-int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl) {
-    auto key = std::make_pair(ctx->unroll * (inl ? 1 : -1), ctx->block);
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block) {
+    auto key = std::make_pair(unroll * (inl ? 1 : -1), block);
     auto it = ctx->occupancy.find(key);
     int nb;
     if (it != ctx->occupancy.end()) {
         nb = it->second;
     } else {
-        nb = sg_stream_occupancy(ctx->unroll, inl, ctx->block);
+        nb = sg_stream_occupancy(unroll, inl, block);
         ctx->occupancy[key] = nb;
     }
     const int64_t cap = (int64_t)nb * ctx->num_cu;
@@ -235,12 +235,14 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         if (st != SG_OK) { P->plan.valid = false; return st; }
     }
     Plan& plan = P->plan;
-    const int block = ctx->block, unroll = ctx->unroll, C = ctx->substeps;
+    const int block = P->block ? P->block : ctx->block;
+    const int unroll = P->unroll ? P->unroll : ctx->unroll;
+    const int C = P->substeps ? P->substeps : ctx->substeps;
     const int64_t sub_elems = (int64_t)block * 4 * unroll;
     // grid and tile count of one pass: G blocks, each holding R tiles of C sub-tiles
     auto geometry = [&](int64_t n, int& grid, int64_t& ntiles) {
         const int64_t nsub = std::max<int64_t>(1, (n + sub_elems - 1) / sub_elems);
-        grid = stream_grid(ctx, (nsub + C - 1) / C, true);
+        grid = stream_grid(ctx, (nsub + C - 1) / C, true, unroll, block);
         const int64_t R = (nsub + (int64_t)grid * C - 1) / ((int64_t)grid * C);
         ntiles = R * grid;
     };
@@ -254,6 +256,8 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     int nprod = 0;
     for (auto& st : plan.steps) nprod += st.kind == Step::PRODUCT;
     const int64_t nres = (int64_t)plan.insts.size() + nprod;
+    for (auto& ip : plan.insts)
+        if (ip.result_index < 0 || ip.result_index >= nres) return fail(ctx, SG_E_UNSUPPORTED, "plan result index out of range");
     sg_status st = ensure_scratch(ctx, max_tiles, max_tiles * C * MAX_WAVES, nres);
     if (st != SG_OK) return st;
     for (auto* m : plan.mats)
@@ -296,6 +300,7 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
             std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
             t_begin("stream");
             SG_HIP(ctx, sg_launch_stream(a, unroll, true, grid, block, ctx->stream));
+            ctx->last_grid = grid;
             t_end();
             for (auto* o : ip.compacted) o->count_dev = &S.results[ip.result_index].scan_count;
         } else if (step.kind == Step::GEMM) {

@@ -1,0 +1,292 @@
+// Cost model of the plan selector: a 24-64-64-1 float32 MLP with ReLU, trained on measured
+// plan timings (mean squared error, Adam after Kingma and Ba, ICLR 2015) and evaluated for
+// every candidate plan of a chain.
+//
+// Training runs in one workgroup: the whole network (5825 parameters) and a batch of 128
+// samples' activations fit in LDS, so a step is forward, backward and update with only
+// barriers between phases, and every gradient is a sum over the batch in sample order
+// (identical results from run to run).  Inference runs one sample per thread over a grid.
+//
+// Parameter layout (floats): W1[24][64] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sg_runtime.h"
+
+namespace sg {
+
+constexpr int MI = 24, MH = 64, MB = 128;
+constexpr int OW1 = 0, OB1 = OW1 + MI * MH, OW2 = OB1 + MH, OB2 = OW2 + MH * MH, OW3 = OB2 + MH, OB3 = OW3 + MH;
+constexpr int MP = OB3 + 1;  // 5825
+constexpr int HP = MH + 1;   // padded activation row (no LDS bank conflicts)
+
+struct MlpLds {
+    float w[MP];
+    float x[MB][MI + 1];
+    float h1[MB][HP];
+    float h2[MB][HP];   // reused for dH1 after the output layer's gradient
+    float d2[MB][HP];
+    float dy[MB];
+    float loss[MB];
+};
+
+struct AdamArgs {
+    float lr, b1, b2, eps;
+};
+
+// One optimisation step over samples [s0, s0 + B) of X (n x 24) / T (n).  With update == 0
+// it only writes the gradient (for checks); loss_out receives the batch loss.
+__device__ void mlp_step(MlpLds& L, float* __restrict__ P, float* __restrict__ G, float* __restrict__ M1,
+                         float* __restrict__ M2, const float* __restrict__ X, const float* __restrict__ T, int64_t s0,
+                         int B, int step, AdamArgs ad, bool update, double* loss_out) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < MP; i += nt) L.w[i] = P[i];
+    for (int i = tid; i < B * MI; i += nt) L.x[i / MI][i % MI] = X[(s0 + i / MI) * MI + i % MI];
+    __syncthreads();
+    // forward: one sample per thread
+    for (int s = tid; s < B; s += nt) {
+        for (int j = 0; j < MH; ++j) {
+            float a = L.w[OB1 + j];
+            for (int i = 0; i < MI; ++i) a += L.x[s][i] * L.w[OW1 + i * MH + j];
+            L.h1[s][j] = a > 0.f ? a : 0.f;
+        }
+        for (int j = 0; j < MH; ++j) {
+            float a = L.w[OB2 + j];
+            for (int i = 0; i < MH; ++i) a += L.h1[s][i] * L.w[OW2 + i * MH + j];
+            L.h2[s][j] = a > 0.f ? a : 0.f;
+        }
+        float y = L.w[OB3];
+        for (int j = 0; j < MH; ++j) y += L.h2[s][j] * L.w[OW3 + j];
+        const float e = y - T[s0 + s];
+        L.loss[s] = e * e;
+        L.dy[s] = 2.f * e / (float)B;
+        for (int j = 0; j < MH; ++j) L.d2[s][j] = L.h2[s][j] > 0.f ? L.dy[s] * L.w[OW3 + j] : 0.f;
+    }
+    __syncthreads();
+    // output layer gradient (needs h2), then dH1 overwrites h2
+    for (int j = tid; j < MH + 1; j += nt) {
+        float g = 0.f;
+        for (int s = 0; s < B; ++s) g += (j < MH ? L.h2[s][j] : 1.f) * L.dy[s];
+        G[j < MH ? OW3 + j : OB3] = g;
+    }
+    __syncthreads();
+    for (int s = tid; s < B; s += nt) {
+        for (int i = 0; i < MH; ++i) {
+            float a = 0.f;
+            for (int j = 0; j < MH; ++j) a += L.d2[s][j] * L.w[OW2 + i * MH + j];
+            L.h2[s][i] = L.h1[s][i] > 0.f ? a : 0.f;  // dH1
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < MH * MH + MH; k += nt) {
+        float g = 0.f;
+        if (k < MH * MH) {
+            const int i = k / MH, j = k % MH;
+            for (int s = 0; s < B; ++s) g += L.h1[s][i] * L.d2[s][j];
+            G[OW2 + k] = g;
+        } else {
+            const int j = k - MH * MH;
+            for (int s = 0; s < B; ++s) g += L.d2[s][j];
+            G[OB2 + j] = g;
+        }
+    }
+    for (int k = tid; k < MI * MH + MH; k += nt) {
+        float g = 0.f;
+        if (k < MI * MH) {
+            const int i = k / MH, j = k % MH;
+            for (int s = 0; s < B; ++s) g += L.x[s][i] * L.h2[s][j];
+            G[OW1 + k] = g;
+        } else {
+            const int j = k - MI * MH;
+            for (int s = 0; s < B; ++s) g += L.h2[s][j];
+            G[OB1 + j] = g;
+        }
+    }
+    if (tid == 0) {
+        double l = 0.0;
+        for (int s = 0; s < B; ++s) l += L.loss[s];
+        *loss_out = l / B;
+    }
+    __syncthreads();
+    if (!update) return;
+    __threadfence_block();
+    const float c1 = 1.f - powf(ad.b1, (float)step), c2 = 1.f - powf(ad.b2, (float)step);
+    for (int i = tid; i < MP; i += nt) {
+        const float g = G[i];
+        const float m = ad.b1 * M1[i] + (1.f - ad.b1) * g;
+        const float v = ad.b2 * M2[i] + (1.f - ad.b2) * (g * g);
+        M1[i] = m;
+        M2[i] = v;
+        P[i] = L.w[i] - ad.lr * (m / c1) / (sqrtf(v / c2) + ad.eps);
+    }
+    __syncthreads();
+}
+
+// Train for `epochs` passes over n samples in batches of B (the last partial batch included).
+__global__ __launch_bounds__(256) void mlp_train_kernel(float* P, float* G, float* M1, float* M2, const float* X,
+                                                       const float* T, int64_t n, int B, int epochs, int step0,
+                                                       AdamArgs ad, double* epoch_loss) {
+    extern __shared__ char smem[];
+    MlpLds& L = *reinterpret_cast<MlpLds*>(smem);
+    int step = step0;
+    for (int e = 0; e < epochs; ++e) {
+        double tot = 0.0;
+        int64_t cnt = 0;
+        for (int64_t s0 = 0; s0 < n; s0 += B) {
+            const int b = (int)(n - s0 < B ? n - s0 : B);
+            double l = 0.0;
+            mlp_step(L, P, G, M1, M2, X, T, s0, b, ++step, ad, true, epoch_loss + epochs);
+            l = epoch_loss[epochs];
+            tot += l * b;
+            cnt += b;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) epoch_loss[e] = tot / (double)(cnt ? cnt : 1);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void mlp_grad_kernel(float* P, float* G, const float* X, const float* T, int B,
+                                                      double* loss) {
+    extern __shared__ char smem[];
+    MlpLds& L = *reinterpret_cast<MlpLds*>(smem);
+    mlp_step(L, P, G, nullptr, nullptr, X, T, 0, B, 1, AdamArgs{0.f, 0.f, 0.f, 0.f}, false, loss);
+}
+
+__global__ __launch_bounds__(256) void mlp_predict_kernel(const float* __restrict__ P, const float* __restrict__ X,
+                                                         int64_t n, float* __restrict__ Y) {
+    __shared__ float w[MP];
+    for (int i = threadIdx.x; i < MP; i += blockDim.x) w[i] = P[i];
+    __syncthreads();
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float x[MI], h1[MH];
+    for (int i = 0; i < MI; ++i) x[i] = X[s * MI + i];
+    for (int j = 0; j < MH; ++j) {
+        float a = w[OB1 + j];
+        for (int i = 0; i < MI; ++i) a += x[i] * w[OW1 + i * MH + j];
+        h1[j] = a > 0.f ? a : 0.f;
+    }
+    float y = w[OB3];
+    for (int j = 0; j < MH; ++j) {
+        float a = w[OB2 + j];
+        for (int i = 0; i < MH; ++i) a += h1[i] * w[OW2 + i * MH + j];
+        y += (a > 0.f ? a : 0.f) * w[OW3 + j];
+    }
+    Y[s] = y;
+}
+
+}  // namespace sg
+
+using namespace sgrt;
+
+
+extern "C" {
+
+sg_status sg_mlp_create(sg_ctx ctx, const float* params, int64_t nparams, sg_mlp* out) {
+    if (!ctx || !out || !params || nparams != sg::MP) return fail(ctx, SG_E_INVALID, "mlp_create: need 5825 initial parameters");
+    auto* m = new sg_mlp_s();
+    m->ctx = ctx;
+    if (hipMalloc(&m->P, 4 * sg::MP * sizeof(float)) != hipSuccess || hipMalloc(&m->loss, 1024 * sizeof(double)) != hipSuccess) {
+        delete m;
+        return fail(ctx, SG_E_OOM, "mlp_create: allocation");
+    }
+    SG_HIP(ctx, hipMemsetAsync(m->P, 0, 4 * sg::MP * sizeof(float), ctx->stream));
+    SG_HIP(ctx, hipMemcpyAsync(m->P, params, sg::MP * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *out = m;
+    return SG_OK;
+}
+
+sg_status sg_mlp_release(sg_mlp m) {
+    if (!m) return SG_E_INVALID;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    (void)hipFree(m->P);
+    (void)hipFree(m->loss);
+    delete m;
+    return SG_OK;
+}
+
+sg_status sg_mlp_get_params(sg_mlp m, float* params, int64_t nparams) {
+    if (!m || !params || nparams != sg::MP) return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_get_params: bad buffer");
+    SG_HIP(m->ctx, hipMemcpyAsync(params, m->P, sg::MP * sizeof(float), hipMemcpyDeviceToHost, m->ctx->stream));
+    SG_HIP(m->ctx, hipStreamSynchronize(m->ctx->stream));
+    return SG_OK;
+}
+
+// Loss and gradient of one batch (no update): X_dev is B x 24, T_dev B floats (device).
+sg_status sg_mlp_grad(sg_mlp m, const float* X_dev, const float* T_dev, int32_t B, float* grad_host, double* loss) {
+    if (!m || !X_dev || !T_dev || B < 1 || B > sg::MB || !grad_host) return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_grad: bad argument (1 <= B <= 128)");
+    sg_ctx_s* ctx = m->ctx;
+    SG_HIP(ctx, hipFuncSetAttribute((const void*)sg::mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)sizeof(sg::MlpLds)));
+    hipLaunchKernelGGL(sg::mlp_grad_kernel, dim3(1), dim3(256), sizeof(sg::MlpLds), ctx->stream, m->P, m->P + sg::MP,
+                       X_dev, T_dev, (int)B, m->loss);
+    SG_HIP(ctx, hipGetLastError());
+    SG_HIP(ctx, hipMemcpyAsync(grad_host, m->P + sg::MP, sg::MP * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    double l = 0;
+    SG_HIP(ctx, hipMemcpyAsync(&l, m->loss, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (loss) *loss = l;
+    return SG_OK;
+}
+
+// Train on n samples (device X n x 24, T n) for `epochs` epochs in batches of `batch` (<= 128),
+// in the given sample order.  epoch_loss (host, `epochs` doubles) receives the mean loss.
+sg_status sg_mlp_train(sg_mlp m, const float* X_dev, const float* T_dev, int64_t n, int32_t batch, int32_t epochs,
+                       float lr, double* epoch_loss) {
+    if (!m || !X_dev || !T_dev || n < 1 || batch < 1 || batch > sg::MB || epochs < 1 || epochs > 1000)
+        return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_train: bad argument");
+    sg_ctx_s* ctx = m->ctx;
+    sg::AdamArgs ad{lr, 0.9f, 0.999f, 1e-8f};
+    const char* name = "mlp_train";
+    static bool attr_set = false;
+    if (!attr_set) {
+        SG_HIP(ctx, hipFuncSetAttribute((const void*)sg::mlp_train_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)sizeof(sg::MlpLds)));
+        SG_HIP(ctx, hipFuncSetAttribute((const void*)sg::mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)sizeof(sg::MlpLds)));
+        attr_set = true;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->timing) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, ctx->stream);
+    }
+    hipLaunchKernelGGL(sg::mlp_train_kernel, dim3(1), dim3(256), sizeof(sg::MlpLds), ctx->stream, m->P,
+                       m->P + sg::MP, m->P + 2 * sg::MP, m->P + 3 * sg::MP, X_dev, T_dev, n, (int)batch, (int)epochs,
+                       m->step, ad, m->loss);
+    SG_HIP(ctx, hipGetLastError());
+    if (ctx->timing) (void)hipEventRecord(b, ctx->stream);
+    m->step += (int)(epochs * ((n + batch - 1) / batch));
+    std::vector<double> el(epochs);
+    SG_HIP(ctx, hipMemcpyAsync(el.data(), m->loss, epochs * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, a, b) == hipSuccess) { ctx->times[name].ms += ms; ctx->times[name].n += 1; }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    if (epoch_loss) std::memcpy(epoch_loss, el.data(), epochs * sizeof(double));
+    return SG_OK;
+}
+
+// Predictions for n samples (device X n x 24 -> device Y n).
+sg_status sg_mlp_predict(sg_mlp m, const float* X_dev, int64_t n, float* Y_dev) {
+    if (!m || !X_dev || !Y_dev || n < 0) return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_predict: bad argument");
+    if (n == 0) return SG_OK;
+    sg_ctx_s* ctx = m->ctx;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(sg::mlp_predict_kernel, dim3(grid), dim3(256), 0, ctx->stream, m->P, X_dev, n, Y_dev);
+    SG_HIP(ctx, hipGetLastError());
+    return SG_OK;
+}
+
+}  // extern "C"

@@ -79,6 +79,10 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         if (is_collection(r) && r->op != OPN_INPUT && r->op != OPN_MATMUL) mat.insert(r);
     for (auto* s : P->splits)
         if (needed.count(s) && is_collection(s) && is_elementwise(s)) { mat.insert(s); cut.insert(s); }
+    if (P->plan_split && needed.count(P->plan_split) && is_collection(P->plan_split) && is_elementwise(P->plan_split)) {
+        mat.insert(P->plan_split);
+        cut.insert(P->plan_split);
+    }
     for (auto* n : needed) {
         if (n->op == OPN_MATMUL) {
             for (auto* o : n->src)

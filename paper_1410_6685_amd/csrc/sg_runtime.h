@@ -44,6 +44,7 @@ struct sg_ctx_s {
     int unroll = 2;
     int substeps = 8;
     uint32_t epoch = 0;  // host epoch of direct launches
+    int last_grid = 0;
     bool timing = false;
     uint64_t next_id = 0;
     uint64_t generation = 0;  // bumped when a setting that changes plans changes
@@ -163,7 +164,7 @@ void fill_inst(const InstPlan& ip, sg::InstDesc& d, int64_t tile0, int64_t ntile
 void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_values);
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n);
 sg_status assemble_verdicts(sg_program_s* P, const sg::InstResult* results, std::vector<sg_verdict>& V);
-int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl);
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block);
 void retain(sg_node_s* n);
 void retain(sg_fn_s* f);
 void retain(sg_pred_s* p);
@@ -183,11 +184,24 @@ struct sg_program_s {
     std::vector<sg_node_s*> roots;
     std::vector<sgrt::Contract> contracts;
     std::vector<sg_node_s*> splits;
+    // launch plan chosen for this program (autotuner / selector); 0 = the context default
+    int block = 0, unroll = 0, substeps = 0;
+    sg_node_s* plan_split = nullptr;  // extra fusion split point of the plan
     sgrt::Plan plan;
     int32_t next_contract = 0;
 };
 
 struct sg_batch_s;
+
+// Cost-model MLP (24-64-64-1) of the learned plan selector.
+struct sg_mlp_s {
+    sg_ctx_s* ctx = nullptr;
+    float* P = nullptr;    // params | grad | Adam m | Adam v (device)
+    double* loss = nullptr;
+    int step = 0;
+    bool norm_set = false;
+    float mean[24], scale[24], lo[24], hi[24];
+};
 
 #define SG_HIP(ctx, call)                                              \
     do {                                                               \

@@ -244,3 +244,28 @@ def cfg4_instance_inputs(spec: dict, seed: int) -> dict:
 
 def spec_copy(spec: dict) -> dict:
     return copy.deepcopy(spec)
+
+
+# ---- cfg5: cost-model MLP --------------------------------------------------------------------
+
+MLP_SIZES = [(24, 64), (64,), (64, 64), (64,), (64,), ()]
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """He-uniform initial weights (float32) and zero biases for the 24-64-64-1 network, in the
+    layout W1[24][64], b1[64], W2[64][64], b2[64], W3[64], b3 (5825 values)."""
+    g = rng(seed)
+    parts = [g.uniform(-1, 1, (24, 64)) * math.sqrt(6.0 / 24), np.zeros(64),
+             g.uniform(-1, 1, (64, 64)) * math.sqrt(6.0 / 64), np.zeros(64),
+             g.uniform(-1, 1, 64) * math.sqrt(6.0 / 64), np.zeros(1)]
+    return np.concatenate([np.asarray(x, np.float64).reshape(-1) for x in parts]).astype(np.float32)
+
+
+def mlp_synthetic_dataset(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Standardized-looking features (n x 24, float32) and a smooth nonlinear target, for
+    checks of the training kernels independent of measured timings."""
+    g = rng(seed)
+    X = g.standard_normal((n, 24)).astype(np.float32)
+    w = g.standard_normal(24) / math.sqrt(24)
+    T = (np.tanh(X.astype(np.float64) @ w) + 0.1 * X[:, 0].astype(np.float64) ** 2).astype(np.float32)
+    return X, T
