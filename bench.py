@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--interp", action="store_true", help="precompiled interpreter kernel instead of kernels "
+                    "compiled for the program")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is described "
@@ -96,6 +98,8 @@ def main():
     dev = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
     del inp
     ctx = sg.Context(0)
+    ctx.set_specialize(not args.interp)
+    kname = "stream" if args.interp else "stream_spec"
     if args.block or args.unroll:
         ctx.set_launch(args.block, args.unroll)
     built = sg.build_spec(ctx, spec, dev)
@@ -118,7 +122,7 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ctx.set_timing(False)
-        ms, launches = ctx.timing("stream")
+        ms, launches = ctx.timing(kname)
         return wall, ms, launches
 
     print("[bench] timing pre_post", file=sys.stderr, flush=True)
@@ -175,7 +179,8 @@ def main():
                    "n": n, "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "stream_kernel", "avg_launch_ms": round(per_launch_ms, 5)},
+                     "kernel": "stream_kernel" + ("" if args.interp else " (specialized)"),
+                     "avg_launch_ms": round(per_launch_ms, 5)},
         "cpu_baseline": cpu,
         "extras": extras,
     }

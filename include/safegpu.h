@@ -100,12 +100,20 @@ sg_status sg_ctx_set_mode(sg_ctx ctx, sg_mode mode);
  * operation and per contract, every intermediate materialized. */
 sg_status sg_ctx_set_fusion(sg_ctx ctx, int fused);
 /* Launch plan for the streaming kernel: block size (64..1024, multiple of 64) and unroll
- * (1, 2, 4 or 8: 16-byte loads per lane per input and tile).  0 keeps the default. */
+ * (1, 2 or 4: 16-byte loads per lane per input and sub-tile).  0 keeps the default. */
 sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll);
+/* on != 0: run every single-program pass through a kernel compiled at run time (hiprtc) for
+ * that pass's program, as the paper generates one kernel per merged plan (Section 5);
+ * compiled once per device and program, then cached for the process.  on == 0 (default):
+ * the precompiled interpreter kernel.  Results are identical; a compilation failure is
+ * reported as SG_E_DEVICE with the compiler log in sg_last_error.  Batches always use the
+ * interpreter. */
+sg_status sg_ctx_set_specialize(sg_ctx ctx, int on);
 /* Record the device time of every kernel launch with HIP events on the context stream. */
 sg_status sg_ctx_set_timing(sg_ctx ctx, int on);
 /* Accumulated device time (ms) and launch count of one kernel family since the last reset:
- * "stream", "gemm", "product_check", "mlp_train", "mlp_infer". */
+ * "stream" (interpreter), "stream_spec" (specialized), "gemm", "product_check", "mlp_train",
+ * "mlp_infer". */
 sg_status sg_ctx_timing(sg_ctx ctx, const char* kernel, double* total_ms, int64_t* launches);
 sg_status sg_ctx_timing_reset(sg_ctx ctx);
 /* Message for the last error on this context (thread-unsafe, valid until the next call). */

@@ -73,6 +73,7 @@ def _sig(lib):
     sigs = {
         "sg_ctx_create": [c_int, H, P(H)], "sg_ctx_destroy": [H], "sg_ctx_set_mode": [H, c_int],
         "sg_ctx_set_fusion": [H, c_int], "sg_ctx_set_launch": [H, c_int, c_int], "sg_ctx_set_timing": [H, c_int],
+        "sg_ctx_set_specialize": [H, c_int],
         "sg_ctx_timing": [H, c_char_p, P(c_double), P(c_int64)], "sg_ctx_timing_reset": [H],
         "sg_vector_wrap": [H, c_int, H, c_int64, P(H)], "sg_matrix_wrap": [H, c_int, H, c_int64, c_int64, P(H)],
         "sg_vector_from_host": [H, c_int, H, c_int64, P(H)],
@@ -508,6 +509,9 @@ class Context:
 
     def set_launch(self, block: int = 0, unroll: int = 0):
         _check(load().sg_ctx_set_launch(self.h, block, unroll), self.h)
+
+    def set_specialize(self, on: bool):
+        _check(load().sg_ctx_set_specialize(self.h, int(on)), self.h)
 
     def set_timing(self, on: bool):
         _check(load().sg_ctx_set_timing(self.h, int(on)), self.h)

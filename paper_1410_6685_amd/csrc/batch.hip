@@ -18,7 +18,8 @@
 using namespace sg;
 using namespace sgrt;
 
-hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
+hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, size_t lds_bytes,
+                            hipStream_t s);
 hipError_t sg_launch_epoch_bump(uint32_t* e, hipStream_t s);
 
 struct sg_batch_s {
@@ -28,6 +29,7 @@ struct sg_batch_s {
     void* table = nullptr;           // InstDesc[] | SgOp[] | int32 tile_inst[]
     StreamArgs args;
     int grid = 1, block = 256, unroll = 2, substeps = 1;
+    size_t lds = 0;
     int64_t total_tiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -41,7 +43,9 @@ static sg_status batch_free(sg_batch_s* b) {
     if (b->scratch.base) (void)hipFree(b->scratch.base);
     if (b->host) (void)hipHostFree(b->host);
     for (auto* p : b->progs) (void)sg_program_release(p);
+    sg_ctx_s* ctx = b->ctx;
     delete b;
+    ctx_release(ctx);
     return SG_OK;
 }
 
@@ -51,6 +55,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     if (!ctx || !out || n <= 0 || !progs) return fail(ctx, SG_E_INVALID, "batch_create: bad argument");
     auto* b = new sg_batch_s();
     b->ctx = ctx;
+    ctx_retain(ctx);
     b->block = ctx->block;
     b->unroll = ctx->unroll;
     b->substeps = 1;  // one sub-tile per tile: instances are small next to the grid
@@ -58,6 +63,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     std::vector<InstDesc> descs;
     std::vector<SgOp> ops;
     std::vector<int32_t> tile_inst;
+    int max_slots = 0, max_sums = 0, max_cemit = 0;
     for (int i = 0; i < n; ++i) {
         sg_program_s* P = progs[i];
         if (!P || P->ctx != ctx) { batch_free(b); return fail(ctx, SG_E_INVALID, "batch_create: bad program"); }
@@ -72,6 +78,9 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
             if ((st = alloc_output(ctx, m)) != SG_OK) { batch_free(b); return st; }
         InstPlan& ip = plan.insts[0];
         if (ip.n_src) { batch_free(b); return fail(ctx, SG_E_UNSUPPORTED, "batch: sources must have host-known lengths"); }
+        max_slots = std::max(max_slots, (int)ip.slot_kind.size());
+        max_sums = std::max(max_sums, ip.nsum);
+        max_cemit = std::max(max_cemit, inst_cemit(ip));
         const int64_t nt = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);
         InstDesc d;
         fill_inst(ip, d, b->total_tiles, nt, (int)ops.size());
@@ -80,7 +89,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
         for (int64_t t = 0; t < nt; ++t) tile_inst.push_back(i);
         b->total_tiles += nt;
     }
-    sg_status st = alloc_scratch(ctx, b->scratch, b->total_tiles, b->total_tiles * b->substeps * MAX_WAVES, n);
+    sg_status st = alloc_scratch(ctx, b->scratch, b->total_tiles, b->total_tiles, n);
     if (st != SG_OK) { batch_free(b); return st; }
     const size_t db = descs.size() * sizeof(InstDesc), ob = ops.size() * sizeof(SgOp), tb = tile_inst.size() * 4;
     const size_t off_o = (db + 255) & ~(size_t)255, off_t = (off_o + ob + 255) & ~(size_t)255;
@@ -110,8 +119,11 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     a.ninst = n;
     a.substeps = b->substeps;
     a.spread = 1;
-    a.interleave = 1;
-    b->grid = stream_grid(ctx, b->total_tiles, false, b->unroll, b->block);
+    a.lds_slots = max_slots;
+    a.lds_sums = max_sums;
+    a.lds_cemit = max_cemit;
+    b->lds = stream_lds_bytes(max_slots, max_sums, max_cemit, b->substeps, b->block, b->unroll);
+    b->grid = stream_grid(ctx, b->total_tiles, false, b->unroll, b->block, b->lds);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "batch sync"); }
     if (use_graph) {
         // the graph holds only the kernel node (no memset nodes): the kernel leaves its
@@ -124,7 +136,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
         }
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) e = sg_launch_epoch_bump(b->scratch.epoch, cs);
-        if (e == hipSuccess) e = sg_launch_stream(a, b->unroll, false, b->grid, b->block, cs);
+        if (e == hipSuccess) e = sg_launch_stream(a, b->unroll, false, b->grid, b->block, b->lds, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &b->graph);
         if (own) (void)hipStreamDestroy(cs);
         if (e != hipSuccess || e2 != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "graph capture failed"); }
@@ -142,7 +154,7 @@ sg_status sg_batch_launch(sg_batch b) {
         SG_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
     } else {
         SG_HIP(ctx, sg_launch_epoch_bump(b->scratch.epoch, ctx->stream));
-        SG_HIP(ctx, sg_launch_stream(b->args, b->unroll, false, b->grid, b->block, ctx->stream));
+        SG_HIP(ctx, sg_launch_stream(b->args, b->unroll, false, b->grid, b->block, b->lds, ctx->stream));
     }
     return SG_OK;
 }

@@ -19,12 +19,13 @@
 
 using namespace sg;
 
-hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
+hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, size_t lds_bytes,
+                            hipStream_t s);
 hipError_t sg_launch_gemm_f32(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t K, hipStream_t s);
 hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
                                    int64_t N, int64_t K, int64_t nvec, double tol, double* work, InstResult* res,
                                    hipStream_t s);
-int sg_stream_occupancy(int unroll, bool inl, int block);
+int sg_stream_occupancy(int unroll, bool inl, int block, size_t lds_bytes);
 
 namespace sgrt {
 
@@ -54,18 +55,37 @@ float key_to_float(int32_t k) {
 
 }  // namespace
 
-int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block) {
-    auto key = std::make_pair(unroll * (inl ? 1 : -1), block);
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes) {
+    auto key = std::make_tuple(unroll * (inl ? 1 : -1), block, lds_bytes);
     auto it = ctx->occupancy.find(key);
     int nb;
     if (it != ctx->occupancy.end()) {
         nb = it->second;
     } else {
-        nb = sg_stream_occupancy(unroll, inl, block);
+        nb = sg_stream_occupancy(unroll, inl, block, lds_bytes);
         ctx->occupancy[key] = nb;
     }
     const int64_t cap = (int64_t)nb * ctx->num_cu;
     return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cap));
+}
+
+int inst_cemit(const InstPlan& ip) {
+    int k = 0;
+    for (auto& op : ip.prog) k += op.code == EMIT && op.sp != 0 && op.sp == ip.scan_space;
+    return k;
+}
+
+size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll) {
+    return (size_t)(slots + sums) * block * 8 + (size_t)cemit * C * block * 4 * unroll * 4;
+}
+
+// A pass with a scan space keeps one LDS region per wave and sub-tile of a tile (at most
+// 64), and its staged values in at most 64 KiB, so that two blocks fit on a CU.
+int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan) {
+    if (!scan) return C;
+    int c = std::min(C, 64 / (block / 64));
+    while (c > 1 && stream_lds_bytes(slots, sums, cemit, c, block, unroll) > 65536) --c;
+    return std::max(c, 1);
 }
 
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n) {
@@ -237,28 +257,40 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     Plan& plan = P->plan;
     const int block = P->block ? P->block : ctx->block;
     const int unroll = P->unroll ? P->unroll : ctx->unroll;
-    const int C = P->substeps ? P->substeps : ctx->substeps;
+    const int C0 = P->substeps ? P->substeps : ctx->substeps;
     const int64_t sub_elems = (int64_t)block * 4 * unroll;
-    // grid and tile count of one pass: G blocks, each holding R tiles of C sub-tiles
-    auto geometry = [&](int64_t n, int& grid, int64_t& ntiles) {
-        const int64_t nsub = std::max<int64_t>(1, (n + sub_elems - 1) / sub_elems);
-        grid = stream_grid(ctx, (nsub + C - 1) / C, true, unroll, block);
-        const int64_t R = (nsub + (int64_t)grid * C - 1) / ((int64_t)grid * C);
-        ntiles = R * grid;
+    // launch shape of one pass: tiles of C sub-tiles, a grid of G resident blocks
+    struct Geo { int C, grid; int64_t ntiles; size_t lds; };
+    auto geometry = [&](const InstPlan& ip, void* jk) {
+        Geo g;
+        const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
+        g.C = stream_substeps(C0, block, unroll, ns, ip.nsum, ce, ip.scan_space != 0);
+        g.lds = stream_lds_bytes(ns, ip.nsum, ce, g.C, block, unroll);
+        const int64_t nsub = std::max<int64_t>(1, (ip.n + sub_elems - 1) / sub_elems);
+        g.ntiles = (nsub + g.C - 1) / g.C;
+        if (jk) {
+            const int64_t cap = (int64_t)jit_occupancy(jk, block, g.lds) * ctx->num_cu;
+            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, cap));
+        } else {
+            g.grid = stream_grid(ctx, g.ntiles, true, unroll, block, g.lds);
+        }
+        return g;
     };
     int64_t max_tiles = 1;
-    for (auto& ip : plan.insts) {
-        int g;
-        int64_t nt;
-        geometry(ip.n, g, nt);
-        max_tiles = std::max(max_tiles, nt);
-    }
+    // specialized kernels (compiled on first use of a program, then cached)
+    std::vector<void*> jks(plan.insts.size(), nullptr);
+    if (ctx->specialize)
+        for (size_t i = 0; i < plan.insts.size(); ++i) {
+            sg_status js = jit_kernel(ctx, plan.insts[i], unroll, block, &jks[i]);
+            if (js != SG_OK) return js;
+        }
+    for (size_t i = 0; i < plan.insts.size(); ++i) max_tiles = std::max(max_tiles, geometry(plan.insts[i], jks[i]).ntiles);
     int nprod = 0;
     for (auto& st : plan.steps) nprod += st.kind == Step::PRODUCT;
     const int64_t nres = (int64_t)plan.insts.size() + nprod;
     for (auto& ip : plan.insts)
         if (ip.result_index < 0 || ip.result_index >= nres) return fail(ctx, SG_E_UNSUPPORTED, "plan result index out of range");
-    sg_status st = ensure_scratch(ctx, max_tiles, max_tiles * C * MAX_WAVES, nres);
+    sg_status st = ensure_scratch(ctx, max_tiles, max_tiles, nres);
     if (st != SG_OK) return st;
     for (auto* m : plan.mats)
         if ((st = alloc_output(ctx, m)) != SG_OK) return st;
@@ -281,26 +313,28 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     for (auto& step : plan.steps) {
         if (step.kind == Step::STREAM) {
             InstPlan& ip = plan.insts[step.inst];
-            int grid;
-            int64_t ntiles;
-            geometry(ip.n, grid, ntiles);
+            void* jk = jks[step.inst];
+            const Geo g = geometry(ip, jk);
             StreamArgs a;
             std::memset(&a, 0, sizeof(a));
-            a.total_tiles = ntiles;
+            a.total_tiles = g.ntiles;
             a.acc = S.acc + (int64_t)ip.result_index * MAX_SLOTS * MAX_SPREAD;
             a.tags = S.tags;
             a.lookback = S.lookback;
             a.results = S.results + ip.result_index;
             a.ninst = 1;
-            a.substeps = C;
+            a.substeps = g.C;
             a.spread = MAX_SPREAD;
-            a.interleave = grid;
+            a.lds_slots = (int)ip.slot_kind.size();
+            a.lds_sums = ip.nsum;
+            a.lds_cemit = inst_cemit(ip);
             a.epoch_val = next_epoch(ctx);
-            fill_inst(ip, a.inst0, 0, ntiles, 0);
+            fill_inst(ip, a.inst0, 0, g.ntiles, 0);
             std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
-            t_begin("stream");
-            SG_HIP(ctx, sg_launch_stream(a, unroll, true, grid, block, ctx->stream));
-            ctx->last_grid = grid;
+            t_begin(jk ? "stream_spec" : "stream");
+            if (jk) SG_HIP(ctx, jit_launch(jk, a, g.grid, block, g.lds, ctx->stream));
+            else SG_HIP(ctx, sg_launch_stream(a, unroll, true, g.grid, block, g.lds, ctx->stream));
+            ctx->last_grid = g.grid;
             t_end();
             for (auto* o : ip.compacted) o->count_dev = &S.results[ip.result_index].scan_count;
         } else if (step.kind == Step::GEMM) {
@@ -379,6 +413,7 @@ sg_status sg_program_create(sg_ctx ctx, sg_program* out) {
     if (!ctx || !out) return fail(ctx, SG_E_INVALID, "program_create: NULL argument");
     auto* p = new sg_program_s();
     p->ctx = ctx;
+    ctx_retain(ctx);
     *out = p;
     return SG_OK;
 }
@@ -478,7 +513,9 @@ sg_status sg_program_release(sg_program p) {
         release(c.pred);
     }
     for (auto* s : p->splits) release(s);
+    sg_ctx_s* ctx = p->ctx;
     delete p;
+    ctx_release(ctx);
     return SG_OK;
 }
 

@@ -192,23 +192,30 @@ sg_status sg_mlp_create(sg_ctx ctx, const float* params, int64_t nparams, sg_mlp
     if (!ctx || !out || !params || nparams != sg::MP) return fail(ctx, SG_E_INVALID, "mlp_create: need 5825 initial parameters");
     auto* m = new sg_mlp_s();
     m->ctx = ctx;
+    ctx_retain(ctx);
     if (hipMalloc(&m->P, 4 * sg::MP * sizeof(float)) != hipSuccess || hipMalloc(&m->loss, 1024 * sizeof(double)) != hipSuccess) {
-        delete m;
+        (void)sg_mlp_release(m);
         return fail(ctx, SG_E_OOM, "mlp_create: allocation");
     }
-    SG_HIP(ctx, hipMemsetAsync(m->P, 0, 4 * sg::MP * sizeof(float), ctx->stream));
-    SG_HIP(ctx, hipMemcpyAsync(m->P, params, sg::MP * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    hipError_t e = hipMemsetAsync(m->P, 0, 4 * sg::MP * sizeof(float), ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->P, params, sg::MP * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)sg_mlp_release(m);
+        return hip_fail(ctx, e, "mlp_create: upload");
+    }
     *out = m;
     return SG_OK;
 }
 
 sg_status sg_mlp_release(sg_mlp m) {
     if (!m) return SG_E_INVALID;
-    (void)hipStreamSynchronize(m->ctx->stream);
-    (void)hipFree(m->P);
-    (void)hipFree(m->loss);
+    sg_ctx_s* ctx = m->ctx;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (m->P) (void)hipFree(m->P);
+    if (m->loss) (void)hipFree(m->loss);
     delete m;
+    ctx_release(ctx);
     return SG_OK;
 }
 

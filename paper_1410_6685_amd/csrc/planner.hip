@@ -462,6 +462,9 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 prog.push_back(c);
             }
             if ((int)prog.size() > MAX_INLINE_OPS) return fail(ctx, SG_E_UNSUPPORTED, "program longer than 48 operations; add a split point");
+            int ndefer = 0;
+            for (auto& o : prog) ndefer += (o.code == CHK_ALL || o.code == CHK_ANY) && o.sp != 0 && o.sp == ip.scan_space;
+            if (ndefer > MAX_DEFER) return fail(ctx, SG_E_UNSUPPORTED, "more than 2 quantified contracts on a compacted collection in one pass");
             if (nslots > MAX_SLOTS) return fail(ctx, SG_E_UNSUPPORTED, "more than 16 reductions/contracts in one pass");
             ip.result_index = (int)plan->insts.size();
             plan->insts.push_back(ip);

@@ -31,7 +31,7 @@ using namespace sg;
 // ---- kernels (defined in the .hip kernel files) ---------------------------------------------
 hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
 hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s);
-int sg_stream_occupancy(int unroll, bool inl, int block);
+int sg_stream_occupancy(int unroll, bool inl, int block, size_t lds_bytes);
 
 namespace sgrt {
 
@@ -138,6 +138,20 @@ uint32_t next_epoch(sg_ctx_s* ctx) {
 // ---------------------------------------------------------------------------------------------
 // refcounting
 
+// The context lives until its creator and every object made on it have released it, so
+// objects may be released in any order (e.g. by a garbage collector at interpreter exit).
+void ctx_retain(sg_ctx_s* ctx) { if (ctx) ++ctx->refs; }
+void ctx_release(sg_ctx_s* ctx) {
+    if (!ctx || --ctx->refs > 0) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->pool)
+        for (void* p : kv.second) (void)hipFree(p);
+    if (ctx->scratch.base) (void)hipFree(ctx->scratch.base);
+    if (ctx->host_results) (void)hipHostFree(ctx->host_results);
+    for (auto& ev : ctx->events) (void)hipEventDestroy(ev);
+    delete ctx;
+}
+
 void retain(sg_node_s* n) { if (n) ++n->refs; }
 void retain(sg_fn_s* f) { if (f) ++f->refs; }
 void retain(sg_pred_s* p) { if (p) ++p->refs; }
@@ -161,7 +175,9 @@ void release(sg_node_s* n) {
     release(n->src[1]);
     release(n->fn);
     release(n->pred);
+    sg_ctx_s* ctx = n->ctx;
     delete n;
+    ctx_release(ctx);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -309,20 +325,18 @@ sg_status sg_ctx_create(int device, void* hip_stream, sg_ctx* out) {
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->num_cu = prop.multiProcessorCount;
+        std::string arch = prop.gcnArchName;
+        c->arch = arch.substr(0, arch.find(':'));  // e.g. "gfx950" from "gfx950:sramecc+:xnack-"
+    }
     *out = c;
     return SG_OK;
 }
 
 sg_status sg_ctx_destroy(sg_ctx ctx) {
     if (!ctx) return SG_E_INVALID;
-    (void)hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->pool)
-        for (void* p : kv.second) (void)hipFree(p);
-    if (ctx->scratch.base) (void)hipFree(ctx->scratch.base);
-    if (ctx->host_results) (void)hipHostFree(ctx->host_results);
-    for (auto& ev : ctx->events) (void)hipEventDestroy(ev);
-    delete ctx;
+    ctx_release(ctx);
     return SG_OK;
 }
 
@@ -346,6 +360,12 @@ sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll) {
     if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4) return fail(ctx, SG_E_INVALID, "unroll must be 1, 2 or 4");
     if (block) ctx->block = block;
     if (unroll) ctx->unroll = unroll;
+    return SG_OK;
+}
+
+sg_status sg_ctx_set_specialize(sg_ctx ctx, int on) {
+    if (!ctx) return SG_E_INVALID;
+    ctx->specialize = on != 0;
     return SG_OK;
 }
 
@@ -378,6 +398,7 @@ const char* sg_last_error(sg_ctx ctx) { return ctx ? ctx->error.c_str() : g_tls_
 static sg_node_s* new_node(sg_ctx_s* ctx, int op, sg_dtype dt, int64_t n) {
     auto* nd = new sg_node_s();
     nd->ctx = ctx;
+    ctx_retain(ctx);
     nd->op = op;
     nd->dtype = dt;
     nd->n = n;

@@ -6,16 +6,28 @@
 // a different element count.
 //
 // Method (table-driven reduction after Tang, ACM TOMS 15(2), 1989, evaluated in float64):
-//   k = rint(t * 32/ln2), r = t - k*ln2/32 (|r| <= ln2/64), j = k mod 32, m = floor(k/32),
-//   exp(t) = 2^m * 2^(j/32) * exp(r),  exp(r) - 1 by its degree-6 Taylor polynomial.
-// The float64 result y has relative error below 2^-50.  If y lies farther than 2^-46*y
-// from every binary32 rounding boundary, RN32(y) = RN32(exp t).  Otherwise (about one
-// element in 2^22) the value is recomputed in double-double arithmetic (about 2^-100
-// relative error) with the Taylor series to degree 13, which settles the rounding since
-// exp of a nonzero binary32 is never a rounding boundary.
+//   k = rint(t * 64/ln2), r = t - k*ln2/64 (|r| <= ln2/128), j = k mod 64, m = floor(k/64),
+//   exp(t) = 2^m * 2^(j/64) * exp(r),  exp(r) - 1 by its degree-5 Taylor polynomial.
+// The float64 result y has relative error below 2^-51.  If y lies clearly away from every
+// binary32 rounding boundary (checked on its low mantissa bits), RN32(y) = RN32(exp t).
+// Otherwise (about one element in 2^23) the value is recomputed in double-double arithmetic
+// (about 2^-100 relative error; 32 intervals, Taylor series to degree 13), which settles
+// the rounding since exp of a nonzero binary32 is never a rounding boundary.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <cmath>
+#endif
+#ifndef __HIPCC_RTC__
 #include <cstdint>
+#else
+// run-time compilation: fixed-width types without the C library headers
+typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint64_t uint64_t;
+typedef unsigned long uintptr_t;
+#endif
 
 #include "sg_exp_table.h"
 
@@ -107,39 +119,46 @@ SG_HD float exp_rn_slow(float t) {
 }
 
 // Fast path: returns RN32(exp t) and hard = false, or hard = true when t needs the
-// double-double path.
-SG_HD float exp_rn_fast(float t, bool& hard) {
+// double-double path.  `tab` is SG_EXPF_TAB (2^(j/64)); kernels pass a copy in LDS.
+//
+// k is rounded to an integer by adding 1.5*2^52 (its low 32 bits are then k in two's
+// complement), r = t - k*ln2/64 is exact up to the F2 term (|r| <= ln2/128 + 2^-40), and
+// exp(r) - 1 is its degree-5 Taylor polynomial (truncation below 2^-54.5).  The float64
+// result y is then within 2^-51 relative of exp(t), i.e. within 4 units of its last
+// place, so RN32(y) = RN32(exp t) unless the 29 bits below binary32 precision lie within
+// 16 units of the half-way pattern 2^28.  Results below the binary32 normal range take the
+// slow path (their rounding position differs).
+SG_HD float exp_rn_fast(float t, const double* tab, bool& hard) {
     hard = false;
     if (t != t) return t;
     if (t >= u2f(SG_EXP_OVF_BITS)) return __builtin_inff();
     if (t <= u2f(SG_EXP_UNF_BITS)) return 0.0f;
+    if (t < -87.0f) {  // exp(t) < 2^-125.5: near or below the binary32 normal range
+        hard = true;
+        return 0.0f;
+    }
     const double td = (double)t;
-    const double kd = rint(td * SG_EXP_INV_L);
-    const int k = (int)kd;
-    const int j = k & 31;
-    const int m = k >> 5;
-    double r = fma(-kd, SG_EXP_L1, td);
-    r = fma(-kd, SG_EXP_L2, r);
-    double q = fma(r, SG_EXP_IFACT_HI[6], SG_EXP_IFACT_HI[5]);
-    q = fma(q, r, SG_EXP_IFACT_HI[4]);
-    q = fma(q, r, SG_EXP_IFACT_HI[3]);
-    q = fma(q, r, SG_EXP_IFACT_HI[2]);
-    q = fma(q, r, 1.0);
-    const double p = q * r;  // exp(r) - 1
-    const double T = SG_EXP_TAB_HI[j];
-    const double y = fma(T, p, T) * pow2d(m);
-    const float f = (float)y;
-    const double diff = y - (double)f;
-    const double dist = fabs(fabs(diff) - half_gap(f2u(f), diff));
-    hard = dist <= y * 0x1p-46;
-    return f;
+    const double sh = fma(td, SG_EXPF_INV_L, 0x1.8p52);
+    const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, sh);
+    const double kd = sh - 0x1.8p52;
+    double r = fma(-kd, SG_EXPF_L1, td);
+    r = fma(-kd, SG_EXPF_L2, r);
+    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    const double p = fma(q, r * r, r);  // exp(r) - 1
+    const double T = tab[k & 63];
+    const double y = fma(T, p, T) * pow2d(k >> 6);
+    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, y) & 0x1FFFFFFFu;
+    hard = low - (0x10000000u - 16u) <= 32u;
+    return (float)y;
 }
 
 // Correctly rounded binary32 exp.  *slow (if given) is incremented when the double-double
 // path was taken.
 SG_HD float exp_rn(float t, int* slow = nullptr) {
     bool hard;
-    const float f = exp_rn_fast(t, hard);
+    const float f = exp_rn_fast(t, SG_EXPF_TAB, hard);
     if (!hard) return f;
     if (slow) ++*slow;
     return exp_rn_slow(t);

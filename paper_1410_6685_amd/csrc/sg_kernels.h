@@ -7,7 +7,19 @@
 // move data: they define nested index spaces as bit masks; a materialized filter output is
 // written by stream compaction over one "scan space" per instance.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <cstdint>
+#else
+// run-time compilation: fixed-width types without the C library headers
+typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::int64_t int64_t;
+typedef __hip_internal::uint64_t uint64_t;
+typedef unsigned long uintptr_t;
+#define INT32_MAX 2147483647
+#define INT32_MIN (-2147483647 - 1)
+#endif
 
 #ifndef SG_HD
 #define SG_HD __host__ __device__ __forceinline__
@@ -109,14 +121,16 @@ struct StreamArgs {
     int64_t total_tiles;
     uint64_t* acc;              // ninst x MAX_SLOTS x spread accumulators (zero between launches)
     uint64_t* tags;             // total_tiles x TAG_WORDS epoch-tagged per-tile words
-    uint64_t* lookback;         // total_tiles x substeps x waves compaction descriptors
+    uint64_t* lookback;         // total_tiles compaction descriptors (flag 2 | epoch 30 | count 32)
     InstResult* results;        // ninst
     const uint32_t* epoch_ptr;  // graph replays: device word advanced before every launch
     uint32_t epoch_val;         // direct launches: this launch's epoch
     int32_t ninst;
     int32_t substeps;           // sub-steps of blockDim.x * 4U elements per tile
     int32_t spread;             // accumulator copies per slot (spreads same-address atomics)
-    int32_t interleave;         // sub-step c of local tile l covers sub-tile ((l/I)*C + c)*I + l%I
+    int32_t lds_slots;          // per-lane exact accumulators kept in LDS (max over instances)
+    int32_t lds_sums;           // per-lane float64 sums kept in LDS (max over instances)
+    int32_t lds_cemit;          // compacted outputs staged in LDS (max over instances)
     InstDesc inst0;             // single-instance launches: the instance
     SgOp prog0[MAX_INLINE_OPS]; // single-instance launches: its program
 };

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <tuple>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -37,7 +38,10 @@ struct Plan;
 struct sg_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    int refs = 1;  // the creator's reference plus one per node, program, batch and MLP
     int num_cu = 256;
+    std::string arch = "gfx950";  // offload target of run-time compiled kernels
+    bool specialize = false;       // run passes through kernels compiled for their program
     sg_mode mode = SG_MODE_PRE_POST;
     bool fused = true;
     int block = 256;
@@ -55,7 +59,7 @@ struct sg_ctx_s {
     sg::InstResult* host_results = nullptr;
     std::map<std::string, sgrt::KTime> times;
     std::vector<hipEvent_t> events;
-    std::map<std::pair<int, int>, int> occupancy;  // (unroll, block) -> blocks per CU
+    std::map<std::tuple<int, int, size_t>, int> occupancy;  // (±unroll, block, LDS bytes) -> blocks per CU
 };
 
 struct sg_fn_s {
@@ -160,11 +164,22 @@ void dev_free(sg_ctx_s* ctx, void* p);
 sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t chunks, int64_t insts);
 sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t chunks, int64_t insts);
 uint32_t next_epoch(sg_ctx_s* ctx);
+void ctx_retain(sg_ctx_s* ctx);
+// run-time specialized streaming kernels (jit.hip)
+sg_status jit_kernel(sg_ctx_s* ctx, const InstPlan& ip, int unroll, int block, void** handle);
+int jit_occupancy(void* handle, int block, size_t lds);
+hipError_t jit_launch(void* handle, const sg::StreamArgs& a, int grid, int block, size_t lds, hipStream_t s);
+void ctx_release(sg_ctx_s* ctx);
 void fill_inst(const InstPlan& ip, sg::InstDesc& d, int64_t tile0, int64_t ntiles, int prog_off);
 void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_values);
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n);
 sg_status assemble_verdicts(sg_program_s* P, const sg::InstResult* results, std::vector<sg_verdict>& V);
-int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block);
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes);
+// Launch shape of a pass: sub-tiles per tile (clamped when values are staged for
+// compaction) and the dynamic LDS bytes of its per-lane accumulators and staging regions.
+int inst_cemit(const InstPlan& ip);
+int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan);
+size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll);
 void retain(sg_node_s* n);
 void retain(sg_fn_s* f);
 void retain(sg_pred_s* p);

@@ -1,0 +1,678 @@
+#pragma once
+// Fused streaming pass: element functions, zips, filters with stream compaction,
+// reductions and range contracts over one index space, in a single kernel.
+//
+// This is the merged kernel of the execution plan (Section 5, Figures 2 and 3).  The pass
+// is a short register program.  The precompiled kernel interprets it (the opcode is
+// uniform across the block), so one kernel serves every chain and many different chains
+// can share one launch (batched mode); a specialized kernel, compiled at run time for one
+// program, includes the same operation code with constant operands, so that the dispatch
+// and every register index fold away (the paper generates and compiles one kernel per
+// merged plan in the same way).
+//
+// Layout: a sub-tile is blockDim.x * 4U consecutive elements.  Wave w of the block owns the
+// contiguous range [w*U*256, (w+1)*U*256) of the sub-tile; in chunk u, lane l holds
+// elements u*256 + 4l .. u*256 + 4l + 3, loaded with one 16-byte load per input, so every
+// load instruction of a wave reads 1 KiB contiguously.  Element values of one lane live in
+// registers R[reg][4U]; index spaces (filters) and predicates are 4U-bit masks.
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#endif
+
+#include "sg_exp.h"
+#include "sg_kernels.h"
+
+// The pass program: the interpreter by default; a specialized kernel supplies its own,
+// with the facts below as constants (the interpreter takes them from the descriptor).
+#ifndef SG_PROGRAM_INC
+#define SG_PROGRAM_INC "sg_program_interp.inc"
+#endif
+#ifndef SG_GEN_HAS_SCAN
+#define SG_GEN_HAS_SCAN 1  // the program may compact (has a scan space)
+#endif
+#ifndef SG_GEN_NIN
+#define SG_GEN_NIN MAX_IN  // at most this many loaded sources
+#endif
+
+namespace sg {
+
+// ---- small helpers -------------------------------------------------------------------------
+
+__device__ __forceinline__ float uf(uint32_t u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ uint32_t fu(float f) { return __builtin_bit_cast(uint32_t, f); }
+__device__ __forceinline__ int32_t ui(uint32_t u) { return (int32_t)u; }
+
+// order-preserving int32 key of a binary32 value (-0 < +0); NaN handled by the caller
+__device__ __forceinline__ int32_t fkey(uint32_t b) {
+    int32_t s = (int32_t)b;
+    return s >= 0 ? s : (s ^ 0x7FFFFFFF);
+}
+
+__device__ __forceinline__ bool cmp_f(uint8_t op, float x, float c) {
+    switch (op) {
+        case CMP_LT: return x < c;
+        case CMP_LE: return x <= c;
+        case CMP_GT: return x > c;
+        case CMP_GE: return x >= c;
+        case CMP_EQ: return x == c;
+        default: return x != c;
+    }
+}
+__device__ __forceinline__ bool cmp_i(uint8_t op, int32_t x, int32_t c) {
+    switch (op) {
+        case CMP_LT: return x < c;
+        case CMP_LE: return x <= c;
+        case CMP_GT: return x > c;
+        case CMP_GE: return x >= c;
+        case CMP_EQ: return x == c;
+        default: return x != c;
+    }
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int V>
+__device__ __forceinline__ uint32_t all_bits() {
+    return V >= 32 ? 0xFFFFFFFFu : ((1u << V) - 1u);
+}
+
+// Run BODY with `r` bound to the register chosen by a block-uniform index.  Written as a
+// macro so that every case indexes the register file with constants (no private memory).
+#define SG_ON_REG(idx, ...)                                  \
+    switch (idx) {                                           \
+        case 0: { uint32_t(&r)[V] = R[0]; __VA_ARGS__ } break; \
+        case 1: { uint32_t(&r)[V] = R[1]; __VA_ARGS__ } break; \
+        case 2: { uint32_t(&r)[V] = R[2]; __VA_ARGS__ } break; \
+        case 3: { uint32_t(&r)[V] = R[3]; __VA_ARGS__ } break; \
+        default: { uint32_t(&r)[V] = R[4]; __VA_ARGS__ } break; \
+    }
+
+__device__ __forceinline__ uint32_t get_space(const uint32_t (&S)[MAX_SPACES], int s) {
+    switch (s) {
+        case 0: return S[0];
+        case 1: return S[1];
+        case 2: return S[2];
+        case 3: return S[3];
+        case 4: return S[4];
+        case 5: return S[5];
+        case 6: return S[6];
+        default: return S[7];
+    }
+}
+__device__ __forceinline__ void set_space(uint32_t (&S)[MAX_SPACES], int s, uint32_t v) {
+    switch (s) {
+        case 0: S[0] = v; break;
+        case 1: S[1] = v; break;
+        case 2: S[2] = v; break;
+        case 3: S[3] = v; break;
+        case 4: S[4] = v; break;
+        case 5: S[5] = v; break;
+        case 6: S[6] = v; break;
+        default: S[7] = v; break;
+    }
+}
+
+// block-uniform loads from a descriptor in kernarg or global memory
+__device__ __forceinline__ uint32_t uload32(const void* p) {
+    return __builtin_amdgcn_readfirstlane(*(const uint32_t*)p);
+}
+__device__ __forceinline__ uint64_t uload64(const void* p) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(((const uint32_t*)p)[0]);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(((const uint32_t*)p)[1]);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T* uptr(const void* p) {
+    return (T*)(uintptr_t)uload64(p);
+}
+
+// Descriptor reads.  A single-instance launch keeps its descriptor and program in the kernel
+// argument segment: they are read through the segment pointer (address space 4, scalar
+// loads), never through the address of the by-value argument, which would make the
+// compiler copy the whole argument block to private memory.  Batched launches read the
+// descriptor table in global memory with block-uniform loads.
+typedef const __attribute__((address_space(4))) char* kptr;
+
+template <bool INLINE>
+__device__ __forceinline__ uint32_t d32(kptr kb, const char* gb, int off) {
+    if constexpr (INLINE) return *(const __attribute__((address_space(4))) uint32_t*)(kb + off);
+    else return __builtin_amdgcn_readfirstlane(*(const uint32_t*)(gb + off));
+}
+template <bool INLINE>
+__device__ __forceinline__ uint64_t d64(kptr kb, const char* gb, int off) {
+    if constexpr (INLINE) {
+        return *(const __attribute__((address_space(4))) uint64_t*)(kb + off);
+    } else {
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(*(const uint32_t*)(gb + off));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane(*(const uint32_t*)(gb + off + 4));
+        return ((uint64_t)hi << 32) | lo;
+    }
+}
+template <bool INLINE>
+__device__ __forceinline__ uint8_t d8_lane(kptr kb, const char* gb, int off) {  // per-lane index
+    if constexpr (INLINE) return *(const __attribute__((address_space(4))) uint8_t*)(kb + off);
+    else return *(const uint8_t*)(gb + off);
+}
+
+struct Lds {
+    double exptab[64];                       // 2^(j/64) for the exp fast path
+    uint64_t slot[MAX_WAVES][MAX_SLOTS];     // per-wave combines of the per-lane accumulators
+    double sum[MAX_WAVES][MAX_SUMS];         // per-wave sums of the current tile
+    double tsum[TILE_BUF][MAX_SUMS];         // sums of tiles not yet published
+    int64_t tile[TILE_BUF];
+    double fin[MAX_WAVES][MAX_SUMS];
+    uint32_t rcnt[64];                       // kept values per LDS region of the current tile
+    uint32_t roff[64];                       // their exclusive prefix within the tile
+    uint32_t dfirst[MAX_DEFER][64];          // first failing compacted rank per region
+    int64_t excl;                            // the tile's exclusive prefix in the scan space
+};
+
+__device__ __forceinline__ uint64_t tag_word(uint32_t epoch, uint32_t payload) {
+    return ((uint64_t)epoch << 32) | payload;
+}
+
+// ---- the kernel ----------------------------------------------------------------------------
+//
+// A tile is `substeps` consecutive sub-tiles of blockDim.x * 4U elements of one instance.
+// Tiles are assigned statically (block b takes tiles b, b + G, b + 2G, ... of a persistent
+// grid that fits on the device at once), so nothing is handed out through a shared
+// counter: same-address atomics serialize across the chip.  While a sub-tile's results are
+// being combined, the loads of the block's next sub-tile are already in flight (they go
+// into the value registers as soon as the program has finished with them).
+//
+// Accumulators are per lane, in LDS (dynamic part): exact slots (counts, int sums, min/max
+// keys, first indices) are combined over the block once per instance and flushed to device
+// accumulators spread over `spread` copies; float64 sums are combined once per tile in a
+// fixed order (lanes, then waves) and published in epoch-tagged 64-bit words; the block
+// holding an instance's last tile waits until every tile word of the instance carries this
+// launch's epoch (which also proves every contributing block has flushed), adds the sums
+// in tile order and writes the result.  Sums are thus identical from run to run for a
+// given launch configuration.
+//
+// Compaction: each wave packs the kept values of its part of a sub-tile into its own LDS
+// region; at the end of the tile the block's count is published and one wave walks back
+// over the published counts of earlier tiles (a decoupled look-back, 256 descriptors per
+// step) to the tile's exclusive prefix; then every wave copies its regions out, contiguous
+// and coalesced.  Waits only ever target lower-numbered tiles, which are processed in
+// increasing order by blocks that are all resident, so they end; every wait is bounded and
+// reports a device error instead of hanging.
+//
+// Dynamic LDS layout (bytes): [lds_slots][blockDim] u64 | [lds_sums][blockDim] f64 |
+// [lds_cemit][substeps * waves][256U] u32.
+
+constexpr int LB_WINDOW = 4;  // look-back descriptors per lane per step
+
+template <int U, bool INLINE, int LB>
+__global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const StreamArgs A) {
+    constexpr int V = 4 * U;
+    constexpr int RW = 256 * U;  // elements of a wave's part of a sub-tile
+    __shared__ Lds L;
+    extern __shared__ uint64_t dyn[];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int B = blockDim.x;
+    const int nwaves = B >> 6;
+    const int C = A.substeps;
+    const int64_t sub_elems = (int64_t)B * V;
+    const uint32_t epoch = A.epoch_ptr
+        ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(A.epoch_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        : A.epoch_val;
+    const int spread = A.spread;
+    const int sp_idx = (int)(blockIdx.x % (unsigned)spread);
+    const kptr kargs = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+    const kptr kdesc = kargs + __builtin_offsetof(StreamArgs, inst0);
+    const kptr kprog = kargs + __builtin_offsetof(StreamArgs, prog0);
+
+    uint64_t* lacc = dyn;                                        // [slot][B]
+    double* lsum = (double*)(dyn + (int64_t)A.lds_slots * B);    // [sum][B]
+    uint32_t* stage = (uint32_t*)(dyn + (int64_t)(A.lds_slots + A.lds_sums) * B);
+    auto acc_add = [&](int k, uint64_t v) { lacc[k * B + tid] += v; };
+    auto acc_max = [&](int k, uint64_t v) {
+        const uint64_t o = lacc[k * B + tid];
+        lacc[k * B + tid] = v > o ? v : o;
+    };
+
+    // block-uniform state of the current instance
+    int cur = -1, ntl = 0;
+    const char* D = nullptr;     // batched: descriptor in global memory
+    const char* prog = nullptr;  // batched: program in global memory
+    int plen = 0, nin = 0, scan_space = 0, flags = 0, nsum = 0, ns = 0;
+    int64_t n = 0, tile0 = 0, ntiles = 0;
+    // program facts the tile end needs (block-uniform, the same for every sub-tile)
+    int nce = 0, ce_reg0 = 0, ce_reg1 = 0, ce_out0 = 0, ce_out1 = 0;
+    int nd = 0, d_slot0 = 0, d_slot1 = 0;
+
+    for (int k = 0; k < A.lds_slots; ++k) lacc[k * B + tid] = 0;
+    for (int k = 0; k < A.lds_sums; ++k) lsum[k * B + tid] = 0.0;
+    if (tid < 64) L.exptab[tid] = SG_EXPF_TAB[tid];
+    __syncthreads();
+
+    // Combine the block's exact accumulators of instance `cur`, publish its buffered tiles;
+    // the block holding the instance's last tile finalizes.
+    auto flush = [&]() {
+        for (int k = 0; k < ns; ++k) {
+            const uint8_t kind = d8_lane<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, slot_kind) + k);
+            uint64_t v = lacc[k * B + tid];
+            lacc[k * B + tid] = 0;
+            v = kind == SLOT_ADD ? (uint64_t)wave_sum_i64((int64_t)v) : wave_max_u64(v);
+            if (lane == 0) L.slot[wave][k] = v;
+        }
+        __syncthreads();
+        if (tid < ns) {
+            const uint8_t kind = d8_lane<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, slot_kind) + tid);
+            uint64_t v = 0;
+            for (int w = 0; w < nwaves; ++w) {
+                const uint64_t x = L.slot[w][tid];
+                v = kind == SLOT_ADD ? v + x : (x > v ? x : v);
+            }
+            uint64_t* g = A.acc + ((int64_t)cur * MAX_SLOTS + tid) * spread + sp_idx;
+            if (v) {
+                if (kind == SLOT_ADD) (void)__hip_atomic_fetch_add(g, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else (void)__hip_atomic_fetch_max(g, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // accumulator updates complete before the tiles are published
+        __syncthreads();
+        bool has_last = false;
+        for (int q = 0; q < ntl; ++q) has_last |= L.tile[q] == tile0 + ntiles - 1;
+        const int words = 1 + 2 * nsum;
+        for (int idx = tid; idx < ntl * words; idx += B) {
+            const int q = idx / words, w = idx % words;
+            uint32_t payload = 0;
+            if (w > 0) {
+                const uint64_t bits = __builtin_bit_cast(uint64_t, L.tsum[q][(w - 1) >> 1]);
+                payload = ((w - 1) & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits;  // low half first
+            }
+            __hip_atomic_store(&A.tags[L.tile[q] * TAG_WORDS + w], tag_word(epoch, payload), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        ntl = 0;
+        if (!has_last) return;
+        // ---- finalize the instance ----
+        InstResult* res = A.results + cur;
+        for (uint32_t spins = 0;; ++spins) {
+            int ok = 1;
+            for (int64_t q = tid; q < ntiles; q += B)
+                for (int w = 0; w < words; ++w) {
+                    const uint64_t x = __hip_atomic_load(&A.tags[(tile0 + q) * TAG_WORDS + w], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    ok &= (uint32_t)(x >> 32) == epoch;
+                }
+            if (__syncthreads_and(ok)) break;
+            if (spins > (1u << 22)) {
+                if (tid == 0) atomicOr(&res->err, (uint32_t)ERR_FINALIZE_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        for (int k = 0; k < nsum; ++k) {
+            double s = 0.0;
+            for (int64_t q = tid; q < ntiles; q += B) {
+                const uint64_t* tw = A.tags + (tile0 + q) * TAG_WORDS + 1 + 2 * k;
+                const uint64_t lo = __hip_atomic_load(tw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t hi = __hip_atomic_load(tw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s += __builtin_bit_cast(double, ((hi & 0xFFFFFFFFull) << 32) | (lo & 0xFFFFFFFFull));
+            }
+            s = wave_sum_f64(s);
+            if (lane == 0) L.fin[wave][k] = s;
+        }
+        __syncthreads();
+        if (tid < nsum) {
+            double s = 0.0;
+            for (int w = 0; w < nwaves; ++w) s += L.fin[w][tid];
+            res->sum[tid] = s;
+        }
+        const int count_slot = (int)d32<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, count_slot));
+        if (tid < ns) {
+            const uint8_t kind = d8_lane<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, slot_kind) + tid);
+            uint64_t v = 0;
+            uint64_t* g = A.acc + ((int64_t)cur * MAX_SLOTS + tid) * spread;
+            for (int j = 0; j < spread; ++j) {
+                const uint64_t x = __hip_atomic_load(g + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v = kind == SLOT_ADD ? v + x : (x > v ? x : v);
+                if (x) __hip_atomic_store(g + j, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            res->slot[tid] = (int64_t)v;
+            if (tid == count_slot) res->scan_count = (int64_t)v;
+        }
+        __syncthreads();
+    };
+
+    uint32_t R[NREG][V];
+    bool pf = false;  // R[0..nin) already hold the inputs of the next sub-tile
+
+    for (int64_t t = blockIdx.x; t < A.total_tiles; t += gridDim.x) {
+        const int inst = INLINE ? 0 : (int)uload32(A.tile_inst + t);
+        if (inst != cur || ntl == TILE_BUF) {
+            if (cur >= 0) flush();
+            if (inst != cur) {
+                cur = inst;
+                pf = false;
+                D = INLINE ? nullptr : (const char*)(A.insts + inst);
+#define SG_D32(F) d32<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, F))
+#define SG_D64(F) d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, F))
+                prog = INLINE ? nullptr : (const char*)(A.progs + (int)SG_D32(prog_off));
+                plen = (int)SG_D32(prog_len);
+                const int64_t* n_dev = (const int64_t*)(uintptr_t)SG_D64(n_dev);
+                n = n_dev ? (int64_t)uload64(n_dev) : (int64_t)SG_D64(n);
+                tile0 = (int64_t)SG_D64(tile0);
+                ntiles = (int64_t)SG_D64(ntiles);
+                nin = (int)SG_D32(nin);
+                scan_space = (int)SG_D32(scan_space);
+                flags = (int)SG_D32(flags);
+                nsum = (int)SG_D32(nsum);
+                ns = (int)SG_D32(nslots);
+#undef SG_D32
+#undef SG_D64
+            }
+        }
+        const int64_t local = t - tile0;
+        // sub-tiles of this tile that hold elements (the first one always runs, so that an
+        // empty instance still publishes and finalizes)
+        int cend;
+        {
+            const int64_t rem = n - local * C * sub_elems;
+            cend = rem <= 0 ? 1 : (int)((rem + sub_elems - 1) / sub_elems < C ? (rem + sub_elems - 1) / sub_elems : C);
+        }
+
+        for (int c = 0; c < cend; ++c) {
+            const int64_t sub_base = (local * C + c) * sub_elems;
+            const bool full = sub_base + sub_elems <= n;
+            const bool vec = full && (flags & 1);
+            const int64_t e0 = sub_base + (int64_t)wave * RW + lane * 4;
+
+            uint32_t S[MAX_SPACES];
+            uint32_t P0 = 0, P1 = 0, P2 = 0, P3 = 0;
+            uint32_t D0 = 0, D1 = 0;
+
+            auto elem = [&](int v) -> int64_t { return e0 + (v >> 2) * 256 + (v & 3); };
+            auto first_of = [&](uint32_t m) -> uint64_t {
+                if (!m) return ~0ull;
+                return (uint64_t)elem(__builtin_ctz(m));
+            };
+
+            uint32_t inb = 0;
+            if (full) {
+                inb = all_bits<V>();
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) inb |= (elem(v) < n ? 1u : 0u) << v;
+            }
+            S[0] = inb;
+#pragma unroll
+            for (int s = 1; s < MAX_SPACES; ++s) S[s] = 0;
+#pragma unroll
+            for (int k = 0; k < NREG; ++k) {
+                if (k < nin && k < SG_GEN_NIN) {
+                    if (!pf) {
+                        const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
+                        if (vec) {
+#pragma unroll
+                            for (int u = 0; u < U; ++u) {
+                                const uint4 w = *(const uint4*)(q + e0 + u * 256);
+                                R[k][4 * u + 0] = w.x;
+                                R[k][4 * u + 1] = w.y;
+                                R[k][4 * u + 2] = w.z;
+                                R[k][4 * u + 3] = w.w;
+                            }
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) R[k][v] = (inb >> v) & 1u ? q[elem(v)] : 0u;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) R[k][v] = 0u;
+                }
+            }
+            nce = 0;
+            nd = 0;
+
+#include SG_PROGRAM_INC
+
+            // ---------------- compaction: pack kept values into this wave's LDS region ----------
+            if (SG_GEN_HAS_SCAN && scan_space != 0) {
+                const uint32_t keep = get_space(S, scan_space);
+                // rank of value v within the region = (kept values of chunks before u)
+                //   + (kept values of lanes below in chunk u) + (kept values j' < j of this lane)
+                uint32_t lbase[U];
+                uint32_t agg = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    uint32_t below = 0, tot = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const uint64_t b = __ballot((keep >> (4 * u + j)) & 1u);
+                        below += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                        tot += (uint32_t)__builtin_popcountll(b);
+                    }
+                    lbase[u] = agg + below;
+                    agg += tot;
+                }
+                auto rank_of = [&](int v) -> uint32_t {
+                    const int u = v >> 2, jj = v & 3;
+                    const uint32_t lowbits = (keep >> (4 * u)) & ((1u << jj) - 1u);
+                    return lbase[u] + (uint32_t)__builtin_popcount(lowbits);
+                };
+                const int region = c * nwaves + wave;
+                for (int ci = 0; ci < nce; ++ci) {
+                    uint32_t* st = stage + ((int64_t)ci * C * nwaves + region) * RW;
+                    SG_ON_REG(ci == 0 ? ce_reg0 : ce_reg1, _Pragma("unroll") for (int v = 0; v < V; ++v)
+                        if ((keep >> v) & 1u) st[rank_of(v)] = r[v];)
+                }
+                for (int ci = 0; ci < nd; ++ci) {
+                    const uint32_t hit = ci == 0 ? D0 : D1;
+                    uint32_t f = hit ? rank_of(__builtin_ctz(hit)) : 0xFFFFFFFFu;
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) f = min(f, (uint32_t)__shfl_xor(f, o));
+                    if (lane == 0) L.dfirst[ci][region] = f;
+                }
+                if (lane == 0) L.rcnt[region] = agg;
+            }
+
+            // ---------------- start the loads of the block's next sub-tile ----------------
+            {
+                int64_t nb = -1;
+                if (c + 1 < cend) nb = sub_base + sub_elems;
+                else if (INLINE && t + (int64_t)gridDim.x < A.total_tiles) nb = (t + (int64_t)gridDim.x - tile0) * C * sub_elems;
+                pf = nb >= 0 && nb + sub_elems <= n && (flags & 1);
+                if (pf) {
+                    const int64_t ne0 = nb + (int64_t)wave * RW + lane * 4;
+#pragma unroll
+                    for (int k = 0; k < MAX_IN && k < NREG; ++k) {
+                        if (k < nin && k < SG_GEN_NIN) {
+                            const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
+#pragma unroll
+                            for (int u = 0; u < U; ++u) {
+                                const uint4 w = *(const uint4*)(q + ne0 + u * 256);
+                                R[k][4 * u + 0] = w.x;
+                                R[k][4 * u + 1] = w.y;
+                                R[k][4 * u + 2] = w.z;
+                                R[k][4 * u + 3] = w.w;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        // ---------------- tile end: compaction prefix and copy-out -----------------------------
+        if (SG_GEN_HAS_SCAN && scan_space != 0) {
+            __syncthreads();
+            const int nreg = cend * nwaves;  // regions written in this tile (at most 64)
+            if (wave == 0) {
+                const uint32_t cnt = lane < nreg ? L.rcnt[lane] : 0u;
+                uint32_t incl = cnt;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                L.roff[lane] = incl - cnt;
+                const uint64_t total = (uint64_t)__shfl(incl, 63);
+                const uint64_t ep = (uint64_t)(epoch & 0x3FFFFFFFu) << 32;
+                const uint64_t AGG = 1ull << 62, INC = 2ull << 62;
+                int64_t excl = 0;
+                if (t == tile0) {
+                    if (lane == 0) st_relaxed(&A.lookback[t], INC | ep | total);
+                } else {
+                    if (lane == 0) st_relaxed(&A.lookback[t], AGG | ep | total);
+                    // descriptors at distance p + 1 = 1 + 64m + lane, nearest first
+                    int64_t j = t - 1;
+                    for (uint32_t spins = 0;;) {
+                        uint64_t d[LB_WINDOW];
+#pragma unroll
+                        for (int m = 0; m < LB_WINDOW; ++m) {
+                            const int64_t idx = j - 64 * m - lane;
+                            d[m] = idx >= tile0 ? ld_relaxed(&A.lookback[idx]) : (INC | ep);
+                        }
+                        int fi = 64 * LB_WINDOW;  // position of the nearest inclusive descriptor
+                        bool wait = false;
+#pragma unroll
+                        for (int m = 0; m < LB_WINDOW; ++m) {
+                            const bool valid = (d[m] & (0x3FFFFFFFull << 32)) == ep && (d[m] >> 62) != 0;
+                            const uint64_t incm = __ballot(valid && (d[m] >> 62) == 2);
+                            const uint64_t invm = __ballot(!valid);
+                            if (fi == 64 * LB_WINDOW) {
+                                const int f = incm ? __builtin_ctzll(incm) : 64;
+                                const uint64_t need = f >= 63 ? ~0ull : ((2ull << f) - 1ull);
+                                if (invm & need) wait = true;
+                                if (incm) fi = 64 * m + f;
+                            }
+                        }
+                        if (wait) {
+                            if (++spins > (1u << 22)) {
+                                if (lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
+                                excl = -1;  // no prefix: nothing of this tile is written
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            continue;
+                        }
+                        int64_t part = 0;
+#pragma unroll
+                        for (int m = 0; m < LB_WINDOW; ++m)
+                            part += (64 * m + lane <= fi) ? (int64_t)(uint32_t)d[m] : 0;
+                        excl += wave_sum_i64(part);
+                        if (fi < 64 * LB_WINDOW) break;
+                        j -= 64 * LB_WINDOW;
+                    }
+                    // after a timed-out wait the prefix is unknown; publishing the tile's own count
+                    // keeps later tiles from waiting on it too (the launch reports the error)
+                    if (lane == 0)
+                        st_relaxed(&A.lookback[t], INC | ep | (uint64_t)(uint32_t)((excl >= 0 ? (uint64_t)excl : 0) + total));
+                }
+                if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
+                if (lane == 0) L.excl = excl;
+            }
+            __syncthreads();
+            const int64_t excl = L.excl;
+            uint64_t dbest0 = 0, dbest1 = 0;
+            for (int rg = wave; rg < nreg && excl >= 0; rg += nwaves) {
+                const uint32_t cnt = L.rcnt[rg];
+                const int64_t ob = excl + L.roff[rg];
+                for (int ci = 0; ci < nce; ++ci) {
+                    uint32_t* q = (uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1));
+                    const uint32_t* st = stage + ((int64_t)ci * C * nwaves + rg) * RW;
+                    for (uint32_t i = lane; i < cnt; i += 64) q[ob + i] = st[i];
+                }
+                for (int ci = 0; ci < nd; ++ci) {
+                    const uint32_t f = L.dfirst[ci][rg];
+                    if (f != 0xFFFFFFFFu) {
+                        const uint64_t e = ~(uint64_t)(ob + f);
+                        if (ci == 0) dbest0 = e > dbest0 ? e : dbest0;
+                        else dbest1 = e > dbest1 ? e : dbest1;
+                    }
+                }
+            }
+            if (lane == 0) {
+                if (nd > 0 && dbest0) acc_max(d_slot0, dbest0);
+                if (nd > 1 && dbest1) acc_max(d_slot1, dbest1);
+            }
+        }
+        // tile end: its sums, added over the lanes and then the waves in a fixed order, are
+        // buffered for publication
+        for (int k = 0; k < nsum; ++k) {
+            double s = lsum[k * B + tid];
+            lsum[k * B + tid] = 0.0;
+            s = wave_sum_f64(s);
+            if (lane == 0) L.sum[wave][k] = s;
+        }
+        __syncthreads();
+        if (tid < nsum) {
+            double s = 0.0;
+            for (int w = 0; w < nwaves; ++w) s += L.sum[w][tid];
+            L.tsum[ntl][tid] = s;
+        }
+        if (tid == 0) L.tile[ntl] = t;
+        __syncthreads();
+        ++ntl;
+    }
+    if (cur >= 0) flush();
+}
+
+// zero a region of 64-bit words (accumulators, tags, look-back descriptors) without a
+// memset node, so the call can sit inside a captured graph
+__global__ void zero_kernel(uint64_t* p, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// advance the launch epoch of a captured graph (one thread)
+__global__ void epoch_bump_kernel(uint32_t* e) {
+    uint32_t v = (*e + 1u) & 0x3FFFFFFFu;
+    *e = v ? v : 1u;
+}
+
+}  // namespace sg
+

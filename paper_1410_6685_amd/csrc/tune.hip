@@ -23,7 +23,7 @@ using namespace sg;
 using namespace sgrt;
 
 extern "C" sg_status sg_mlp_predict(sg_mlp_s* m, const float* X_dev, int64_t n, float* Y_dev);
-int sg_stream_occupancy(int unroll, bool inl, int block);
+int sg_stream_occupancy(int unroll, bool inl, int block, size_t lds_bytes);
 
 namespace {
 
@@ -141,7 +141,15 @@ sg_status features(sg_program_s* P, const sg_plan* plan, const std::vector<sg_no
     for (auto& ip : tmp.insts) bytes += 4.0 * (double)(ip.sources.size() + ip.outs.size());
     f[21] = (float)tmp.insts.size();
     f[22] = (float)bytes;
-    f[23] = (float)sg_stream_occupancy(plan->unroll, true, plan->block);
+    int occ = 0;
+    for (auto& ip : tmp.insts) {
+        const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
+        const int C = stream_substeps(plan->substeps, plan->block, plan->unroll, ns, ip.nsum, ce, ip.scan_space != 0);
+        const int o = sg_stream_occupancy(plan->unroll, true, plan->block,
+                                          stream_lds_bytes(ns, ip.nsum, ce, C, plan->block, plan->unroll));
+        occ = occ == 0 ? o : std::min(occ, o);
+    }
+    f[23] = (float)occ;  // resident blocks per CU of the tightest pass
     return SG_OK;
 }
 

@@ -45,13 +45,16 @@ def test_batch_matches_oracle_and_single(sg, ctx, use_graph):
             k += nv
         # eager work between replays
         ctx.execute(builts[0]["s"])
-    # per-instance execution gives identical results
-    for i in (0, 5, 42, 149):
-        s_batch = builts[i]["s"].shadow() if statuses[i] != "pre_violated" else None
-        st, _ = builts[i].program.execute()
+    # per-instance execution gives the same status and verdicts (bit-exact) and sums within
+    # the tolerance: the float64 addition order differs between launch configurations
+    k0 = [0]
+    for sp in specs:
+        k0.append(k0[-1] + len(sp["contracts"]))
+    for i in (0, 5, 42, 77, 149):
+        st, vs = builts[i].program.execute()
         assert st == statuses[i]
-        if s_batch is not None:
-            assert builts[i]["s"].shadow() == s_batch
+        assert [(v.holds, v.first_index) for v in vs] == [(v.holds, v.first_index) for v in verdicts[k0[i]:k0[i + 1]]]
+        compare(specs[i], builts[i], st, vs, oracle.evaluate(specs[i], inputs[i]))
 
 
 def test_batch_with_launch_configs(sg, ctx):

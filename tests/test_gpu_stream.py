@@ -10,9 +10,13 @@ from gpu_util import compare, run_spec, say, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx(sg):
-    return sg.Context(0)
+@pytest.fixture(scope="module", params=[False, True], ids=["interp", "spec"])
+def ctx(sg, request):
+    """Every test runs on the precompiled interpreter and on kernels compiled for the program."""
+    c = sg.Context(0)
+    c.set_specialize(request.param)
+    c.specialized = request.param
+    return c
 
 
 SIZES = [0, 1, 63, 64, 65, 1000, 4095, 4096, 4097, 65537, 300001]
@@ -166,3 +170,21 @@ def test_sum_is_deterministic(sg, ctx):
         built.program.execute()
         vals.add(built["s"].shadow())
     assert len(vals) == 1
+
+
+def test_pass_runs_on_the_selected_kernel(sg, ctx):
+    spec = W.cfg1_spec(5000)
+    inp = W.cfg1_inputs(5000)
+    ctx.set_timing(True)
+    ctx.timing_reset()
+    try:
+        built, status, verdicts, _ = run_spec(sg, ctx, spec, inp)
+        spec_launches = ctx.timing("stream_spec")[1]
+        interp_launches = ctx.timing("stream")[1]
+    finally:
+        ctx.set_timing(False)
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
+    if ctx.specialized:
+        assert spec_launches >= 1 and interp_launches == 0
+    else:
+        assert interp_launches >= 1 and spec_launches == 0
