@@ -66,6 +66,171 @@ def cpu_baseline(n_sample: int) -> dict:
             "sample": f"cfg2 chain + sortedness at n=2^{int(np.log2(n_sample))} ({dt:.1f} s, numpy float64, one thread)"}
 
 
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---- batched uneven instances -------------------------------------------------------------------
+
+def cfg4_build(ctx, count: int, seed: int = 41):
+    """10,000-instance workload: seeded chains over uniform[-1,1) inputs (lengths log-uniform in
+    [2^8, 2^20]), all inputs in one device buffer (each view 64-element aligned)."""
+    import numpy as np
+    import torch
+
+    import paper_1410_6685_amd as sg
+    import workloads as W
+
+    lengths = W.cfg4_lengths(count, seed)
+    specs = W.cfg4_instances(count, seed, seed + 1, lengths)
+    offs, total = [], 0
+    for sp in specs:
+        o = []
+        for inp in sp["inputs"]:
+            o.append(total)
+            total += (inp["n"] + 63) // 64 * 64
+        offs.append(o)
+    buf = torch.empty(total, dtype=torch.float32, device="cuda")
+    builts, nbytes = [], 0
+    for i, sp in enumerate(specs):
+        host = W.cfg4_instance_inputs(sp, 1000 + i)
+        views = {}
+        for k, inp in enumerate(sp["inputs"]):
+            v = buf[offs[i][k]:offs[i][k] + inp["n"]]
+            v.copy_(torch.from_numpy(host[inp["name"]]))
+            views[inp["name"]] = v
+            nbytes += 4 * inp["n"]
+        builts.append(sg.build_spec(ctx, sp, views))
+    torch.cuda.synchronize()
+    return specs, builts, buf, nbytes, int(lengths.sum())
+
+
+def run_cfg4(ctx, count: int, steps: int, warmup: int) -> dict:
+    """One graph-captured persistent launch for all instances (launch shape chosen by timing
+    the candidates: the batch autotuner) vs one launch per instance."""
+    import torch
+
+    import paper_1410_6685_amd as sg
+
+    log(f"cfg4: building {count} instances")
+    specs, builts, _, nbytes, nelem = cfg4_build(ctx, count)
+    progs = [b.program for b in builts]
+    ctx.set_mode("pre_post")
+
+    def time_batch(batch, k):
+        for _ in range(2):
+            batch.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            batch.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    tuned = []
+    for block, unroll in [(256, 1), (256, 2), (256, 4), (512, 2), (1024, 1)]:
+        ctx.set_launch(block, unroll)
+        b = sg.Batch(ctx, progs, use_graph=True)
+        tuned.append((time_batch(b, 3), block, unroll))
+        del b
+    tuned.sort()
+    _, block, unroll = tuned[0]
+    ctx.set_launch(block, unroll)
+    batch = sg.Batch(ctx, progs, use_graph=True)
+    statuses, _ = batch.run()
+    log(f"cfg4: timing {steps} graph launches (block {block}, unroll {unroll})")
+    ms_batch = time_batch(batch, max(steps, 3))
+    log("cfg4: timing per-instance launches")
+    for p in progs[:50]:
+        p.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in progs:
+        p.execute()
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3
+    ctx.set_launch(256, 2)
+    return {"instances": count, "elements": nelem, "algorithmic_bytes": nbytes,
+            "batched_graph_ms": round(ms_batch, 4), "batched_GBs": round(nbytes / ms_batch / 1e6, 2),
+            "per_instance_ms": round(ms_single, 3), "per_instance_GBs": round(nbytes / ms_single / 1e6, 2),
+            "speedup": round(ms_single / ms_batch, 2), "autotuned_launch": {"block": block, "unroll": unroll},
+            "autotune_candidates_ms": [[b, u, round(t, 4)] for t, b, u in tuned],
+            "violated_instances": int(sum(st != "ok" for st in statuses))}
+
+
+# ---- learned plan selector ------------------------------------------------------------------------
+
+def run_cfg5(ctx, n_train: int, n_test: int, seed: int = 51) -> dict:
+    """Cost model trained on the autotuner's timings of seeded random chains; regret of its
+    choice on held-out chains, fallback rate, and gain over the default plan."""
+    import numpy as np
+    import torch
+
+    import paper_1410_6685_amd as sg
+    from paper_1410_6685_amd import selector
+    import workloads as W
+
+    nmax = 1 << 28
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    bufs = {"f32": [torch.rand(nmax, generator=g, device="cuda") * 2 - 1 for _ in range(2)],
+            "i32": [torch.randint(-50000, 50001, (nmax,), generator=g, device="cuda", dtype=torch.int32)
+                    for _ in range(2)]}
+
+    train_specs = []
+
+    def programs(count, s0):
+        lengths = W.selector_lengths(count, s0)
+        out = []
+        for i, n in enumerate(lengths):
+            sp = W.selector_chain_spec(int(n), s0 * 100003 + i)
+            if s0 == seed:
+                train_specs.append(sp)
+            dt = sp["inputs"][0]["dtype"]
+            views = {inp["name"]: bufs[dt][k][:inp["n"]] for k, inp in enumerate(sp["inputs"])}
+            out.append(sg.build_spec(ctx, sp, views))
+        return out
+
+    ctx.set_specialize(False)
+    ctx.set_mode("pre_post")
+    log(f"cfg5: timing candidate plans of {n_train} training chains")
+    t0 = time.perf_counter()
+    train_b = programs(n_train, seed)
+    rejected = []
+    tr = selector.collect([b.program for b in train_b], progress=500, rejected=rejected)
+    for i, p, msg in rejected[:3]:
+        log(f"cfg5: plan {p} refused for chain {i} ({msg}): {json.dumps(train_specs[i])}")
+    t_collect = time.perf_counter() - t0
+    X, y = tr.flat()
+    log(f"cfg5: training the cost model on {len(y)} samples")
+    t0 = time.perf_counter()
+    net, norm, losses = selector.train(ctx, tr, W.mlp_init_params(seed), epochs=60)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del train_b
+    log(f"cfg5: held-out chains ({n_test})")
+    test_b = programs(n_test, seed + 1)
+    te = selector.collect([b.program for b in test_b], progress=500, rejected=rejected)
+    ev = selector.evaluate(net, [b.program for b in test_b], te)
+    # inference cost of one choice (features + forward of every candidate plan)
+    t0 = time.perf_counter()
+    for b, plans in zip(test_b[:200], te.plans[:200]):
+        net.select(b.program, plans, 0.01)
+    t_infer = (time.perf_counter() - t0) / min(200, len(test_b))
+    Xt, yt = te.flat()
+    pred = net.predict(torch.from_numpy(norm.apply(Xt)).cuda()).cpu().numpy()
+    return {"train_chains": n_train, "train_samples": int(len(y)), "test_chains": n_test,
+            "test_samples": int(len(yt)), "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
+            "final_train_mse_log_us": round(float(losses[-1]), 5),
+            "test_mse_log_us": round(float(np.mean((pred - yt) ** 2)), 5),
+            "fallback_rate": round(ev.fallback_rate, 4), "regret_geomean_pct": round(100 * ev.regret_geomean, 3),
+            "regret_p90_pct": round(100 * ev.regret_p90, 3),
+            "regret_learned_only_geomean_pct": round(100 * ev.regret_learned_only, 3),
+            "top1_rate": round(ev.top1, 4), "gain_vs_default_plan": round(ev.gain_vs_default, 4),
+            "select_ms_per_chain": round(1e3 * t_infer, 3), "plans_refused": len(rejected)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +242,9 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cfg4-instances", type=int, default=10_000, help="0 skips the batched workload")
+    ap.add_argument("--cfg5-train", type=int, default=1500, help="training chains (0 skips the selector)")
+    ap.add_argument("--cfg5-test", type=int, default=500)
     ap.add_argument("--interp", action="store_true", help="precompiled interpreter kernel instead of kernels "
                     "compiled for the program")
     args = ap.parse_args()
@@ -155,6 +323,15 @@ def main():
     extras["sorted_first_violation"] = int(verdicts[3].first_index)
     extras["stream_launches_per_step"] = launches_per_step
     extras["stream_kernel_ms_per_step"] = round(k_ms / args.steps, 5)
+    extras["launch_shape"] = dict(zip(("grid", "block", "unroll", "substeps", "lds_bytes"), ctx.last_launch()))
+    del built, prog, dev
+    if not args.no_extras and args.cfg4_instances > 0:
+        ctx.set_specialize(False)
+        extras["cfg4_batched"] = run_cfg4(ctx, args.cfg4_instances, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_extras and args.cfg5_train > 0:
+        extras["cfg5_selector"] = run_cfg5(ctx, args.cfg5_train, args.cfg5_test)
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:

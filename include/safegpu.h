@@ -116,6 +116,11 @@ sg_status sg_ctx_set_timing(sg_ctx ctx, int on);
  * "mlp_infer". */
 sg_status sg_ctx_timing(sg_ctx ctx, const char* kernel, double* total_ms, int64_t* launches);
 sg_status sg_ctx_timing_reset(sg_ctx ctx);
+/* Shape of the last streaming-kernel launch on this context (single-program passes): grid
+ * and block size, unroll, sub-tiles per tile and dynamic LDS bytes per block.  Any out
+ * pointer may be NULL. */
+sg_status sg_ctx_last_launch(sg_ctx ctx, int32_t* grid, int32_t* block, int32_t* unroll, int32_t* substeps,
+                             int64_t* lds_bytes);
 /* Message for the last error on this context (thread-unsafe, valid until the next call). */
 const char* sg_last_error(sg_ctx ctx);
 

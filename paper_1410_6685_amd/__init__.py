@@ -74,6 +74,7 @@ def _sig(lib):
         "sg_ctx_create": [c_int, H, P(H)], "sg_ctx_destroy": [H], "sg_ctx_set_mode": [H, c_int],
         "sg_ctx_set_fusion": [H, c_int], "sg_ctx_set_launch": [H, c_int, c_int], "sg_ctx_set_timing": [H, c_int],
         "sg_ctx_set_specialize": [H, c_int],
+        "sg_ctx_last_launch": [H, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int64)],
         "sg_ctx_timing": [H, c_char_p, P(c_double), P(c_int64)], "sg_ctx_timing_reset": [H],
         "sg_vector_wrap": [H, c_int, H, c_int64, P(H)], "sg_matrix_wrap": [H, c_int, H, c_int64, c_int64, P(H)],
         "sg_vector_from_host": [H, c_int, H, c_int64, P(H)],
@@ -520,6 +521,12 @@ class Context:
         ms, n = c_double(), c_int64()
         _check(load().sg_ctx_timing(self.h, kernel.encode(), byref(ms), byref(n)), self.h)
         return ms.value, n.value
+
+    def last_launch(self):
+        """(grid, block, unroll, substeps, lds_bytes) of the last streaming launch."""
+        g, b, u, c, l = c_int32(), c_int32(), c_int32(), c_int32(), c_int64()
+        _check(load().sg_ctx_last_launch(self.h, byref(g), byref(b), byref(u), byref(c), byref(l)), self.h)
+        return g.value, b.value, u.value, c.value, l.value
 
     def timing_reset(self):
         _check(load().sg_ctx_timing_reset(self.h), self.h)

@@ -59,7 +59,6 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     b->block = ctx->block;
     b->unroll = ctx->unroll;
     b->substeps = 1;  // one sub-tile per tile: instances are small next to the grid
-    const int64_t tile_elems = (int64_t)b->block * 4 * b->unroll;
     std::vector<InstDesc> descs;
     std::vector<SgOp> ops;
     std::vector<int32_t> tile_inst;
@@ -81,6 +80,19 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
         max_slots = std::max(max_slots, (int)ip.slot_kind.size());
         max_sums = std::max(max_sums, ip.nsum);
         max_cemit = std::max(max_cemit, inst_cemit(ip));
+    }
+    // the per-lane accumulators and staging buffers of every instance must fit in LDS
+    for (;; b->unroll /= 2) {
+        b->lds = stream_lds_bytes(max_slots, max_sums, max_cemit, b->substeps, b->block, b->unroll);
+        if (b->lds <= kMaxDynamicLds || b->unroll == 1) break;
+    }
+    if (b->lds > kMaxDynamicLds) {
+        batch_free(b);
+        return fail(ctx, SG_E_UNSUPPORTED, "batch needs more LDS than a block has; use a smaller block");
+    }
+    const int64_t tile_elems = (int64_t)b->block * 4 * b->unroll;
+    for (int i = 0; i < n; ++i) {
+        InstPlan& ip = b->progs[i]->plan.insts[0];
         const int64_t nt = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);
         InstDesc d;
         fill_inst(ip, d, b->total_tiles, nt, (int)ops.size());
@@ -122,7 +134,6 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     a.lds_slots = max_slots;
     a.lds_sums = max_sums;
     a.lds_cemit = max_cemit;
-    b->lds = stream_lds_bytes(max_slots, max_sums, max_cemit, b->substeps, b->block, b->unroll);
     b->grid = stream_grid(ctx, b->total_tiles, false, b->unroll, b->block, b->lds);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "batch sync"); }
     if (use_graph) {

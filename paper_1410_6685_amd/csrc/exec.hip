@@ -258,33 +258,39 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     const int block = P->block ? P->block : ctx->block;
     const int unroll = P->unroll ? P->unroll : ctx->unroll;
     const int C0 = P->substeps ? P->substeps : ctx->substeps;
-    const int64_t sub_elems = (int64_t)block * 4 * unroll;
-    // launch shape of one pass: tiles of C sub-tiles, a grid of G resident blocks
-    struct Geo { int C, grid; int64_t ntiles; size_t lds; };
-    auto geometry = [&](const InstPlan& ip, void* jk) {
-        Geo g;
-        const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
-        g.C = stream_substeps(C0, block, unroll, ns, ip.nsum, ce, ip.scan_space != 0);
-        g.lds = stream_lds_bytes(ns, ip.nsum, ce, g.C, block, unroll);
-        const int64_t nsub = std::max<int64_t>(1, (ip.n + sub_elems - 1) / sub_elems);
-        g.ntiles = (nsub + g.C - 1) / g.C;
-        if (jk) {
-            const int64_t cap = (int64_t)jit_occupancy(jk, block, g.lds) * ctx->num_cu;
-            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, cap));
-        } else {
-            g.grid = stream_grid(ctx, g.ntiles, true, unroll, block, g.lds);
-        }
-        return g;
-    };
+    // launch shape of one pass: unroll U, tiles of C sub-tiles, a grid of G resident blocks;
+    // a pass whose per-lane accumulators and staging buffers would not fit in LDS runs with
+    // a smaller unroll
+    struct Geo { int U, C, grid; int64_t ntiles; size_t lds; };
+    std::vector<Geo> geo(plan.insts.size());
+    std::vector<void*> jks(plan.insts.size(), nullptr);  // specialized kernels (compiled once, cached)
     int64_t max_tiles = 1;
-    // specialized kernels (compiled on first use of a program, then cached)
-    std::vector<void*> jks(plan.insts.size(), nullptr);
-    if (ctx->specialize)
-        for (size_t i = 0; i < plan.insts.size(); ++i) {
-            sg_status js = jit_kernel(ctx, plan.insts[i], unroll, block, &jks[i]);
+    for (size_t i = 0; i < plan.insts.size(); ++i) {
+        const InstPlan& ip = plan.insts[i];
+        Geo& g = geo[i];
+        const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
+        for (g.U = unroll;; g.U /= 2) {
+            g.C = stream_substeps(C0, block, g.U, ns, ip.nsum, ce, ip.scan_space != 0);
+            g.lds = stream_lds_bytes(ns, ip.nsum, ce, g.C, block, g.U);
+            if (g.lds <= kMaxDynamicLds || g.U == 1) break;
+        }
+        if (g.lds > kMaxDynamicLds)
+            return fail(ctx, SG_E_UNSUPPORTED, "pass needs more LDS than a block has (per-lane accumulators); use a smaller block");
+        if (ctx->specialize) {
+            sg_status js = jit_kernel(ctx, ip, g.U, block, &jks[i]);
             if (js != SG_OK) return js;
         }
-    for (size_t i = 0; i < plan.insts.size(); ++i) max_tiles = std::max(max_tiles, geometry(plan.insts[i], jks[i]).ntiles);
+        const int64_t sub_elems = (int64_t)block * 4 * g.U;
+        const int64_t nsub = std::max<int64_t>(1, (ip.n + sub_elems - 1) / sub_elems);
+        g.ntiles = (nsub + g.C - 1) / g.C;
+        if (jks[i]) {
+            const int64_t cap = (int64_t)jit_occupancy(jks[i], block, g.lds) * ctx->num_cu;
+            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, cap));
+        } else {
+            g.grid = stream_grid(ctx, g.ntiles, true, g.U, block, g.lds);
+        }
+        max_tiles = std::max(max_tiles, g.ntiles);
+    }
     int nprod = 0;
     for (auto& st : plan.steps) nprod += st.kind == Step::PRODUCT;
     const int64_t nres = (int64_t)plan.insts.size() + nprod;
@@ -314,7 +320,7 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         if (step.kind == Step::STREAM) {
             InstPlan& ip = plan.insts[step.inst];
             void* jk = jks[step.inst];
-            const Geo g = geometry(ip, jk);
+            const Geo& g = geo[step.inst];
             StreamArgs a;
             std::memset(&a, 0, sizeof(a));
             a.total_tiles = g.ntiles;
@@ -333,8 +339,12 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
             std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
             t_begin(jk ? "stream_spec" : "stream");
             if (jk) SG_HIP(ctx, jit_launch(jk, a, g.grid, block, g.lds, ctx->stream));
-            else SG_HIP(ctx, sg_launch_stream(a, unroll, true, g.grid, block, g.lds, ctx->stream));
+            else SG_HIP(ctx, sg_launch_stream(a, g.U, true, g.grid, block, g.lds, ctx->stream));
             ctx->last_grid = g.grid;
+            ctx->last_block = block;
+            ctx->last_unroll = g.U;
+            ctx->last_substeps = g.C;
+            ctx->last_lds = g.lds;
             t_end();
             for (auto* o : ip.compacted) o->count_dev = &S.results[ip.result_index].scan_count;
         } else if (step.kind == Step::GEMM) {

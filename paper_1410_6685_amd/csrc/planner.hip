@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <set>
@@ -102,6 +103,12 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
     }
 
     // ---- passes ------------------------------------------------------------------------
+    // Element-wise nodes joined by register operands form one pass each.  Passes that read a
+    // common collection, or that read only input collections of one length, then share one
+    // pass (each input is read once) unless one of them reads what the other writes, their
+    // index spaces differ, or the joint pass would exceed the kernel's limits (then the plan
+    // is rebuilt without sharing).
+    bool hmerge = fused;
     for (int attempt = 0; attempt < 16; ++attempt) {
         DSU dsu;
         std::map<sg_node_s*, int> vnode;                          // compute vertex of a node
@@ -112,7 +119,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         std::sort(elem.begin(), elem.end(), [](sg_node_s* a, sg_node_s* b) { return a->id < b->id; });
         for (auto* n : elem) vnode[n] = dsu.add();
         auto src_vertex = [&](sg_node_s* o, long key) {
-            auto k = std::make_pair(o, fused ? 0L : key);
+            auto k = std::make_pair(o, key);
             auto it = vsrc.find(k);
             if (it != vsrc.end()) return it->second;
             int v = dsu.add();
@@ -148,6 +155,80 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         std::set<int> roots_set;
         for (auto& kv : comp_nodes) roots_set.insert(kv.first);
         for (auto& kv : comp_contracts) roots_set.insert(kv.first);
+        if (hmerge) {
+            std::vector<int> roots(roots_set.begin(), roots_set.end());
+            auto unique_srcs = [&](int r) {
+                std::vector<sg_node_s*> v = comp_srcs[r];
+                std::sort(v.begin(), v.end());
+                v.erase(std::unique(v.begin(), v.end()), v.end());
+                return v;
+            };
+            // producer component of every node computed in a pass
+            std::map<sg_node_s*, int> comp_of;
+            for (int r : roots)
+                for (auto* x : comp_nodes[r]) comp_of[x] = r;
+            // is `x` (a pass source) written by component `from`, directly or through products?
+            std::function<bool(sg_node_s*, int)> made_in = [&](sg_node_s* x, int from) {
+                if (!x) return false;
+                auto it = comp_of.find(x);
+                if (it != comp_of.end()) return it->second == from;
+                if (x->op == OPN_MATMUL) return made_in(x->src[0], from) || made_in(x->src[1], from);
+                return false;
+            };
+            // does component `to` read (transitively) what component `from` writes?
+            std::function<bool(int, int, std::set<int>&)> reaches = [&](int from, int to, std::set<int>& seen) {
+                if (from == to) return true;
+                if (!seen.insert(from).second) return false;
+                for (int r : roots) {
+                    if (r == from) continue;
+                    for (auto* x : unique_srcs(r))
+                        if (made_in(x, from) && reaches(r, to, seen)) return true;
+                }
+                return false;
+            };
+            auto compatible = [&](int a, int b) {
+                std::vector<sg_node_s*> all = unique_srcs(a), sb = unique_srcs(b);
+                if (all.empty() || sb.empty()) return false;
+                bool shared = false, inputs_only = true;
+                for (auto* x : sb) shared |= std::find(all.begin(), all.end(), x) != all.end();
+                all.insert(all.end(), sb.begin(), sb.end());
+                std::sort(all.begin(), all.end());
+                all.erase(std::unique(all.begin(), all.end()), all.end());
+                if ((int)all.size() > MAX_IN) return false;
+                sg_node_s* s0 = all[0];
+                for (auto* x : all) {
+                    inputs_only &= x->op == OPN_INPUT;
+                    if (x->n != s0->n) return false;
+                    const bool cx = x->op == OPN_FILTER, c0 = s0->op == OPN_FILTER;
+                    if (cx != c0 || (cx && x != s0 && x->space != s0->space)) return false;
+                }
+                if (!shared && !inputs_only) return false;
+                std::set<int> s1, s2;
+                return !reaches(a, b, s1) && !reaches(b, a, s2);
+            };
+            for (bool merged = true; merged;) {
+                merged = false;
+                for (size_t i = 0; i < roots.size() && !merged; ++i)
+                    for (size_t j = i + 1; j < roots.size() && !merged; ++j) {
+                        const int a = roots[i], b = roots[j];
+                        if (!compatible(a, b)) continue;
+                        for (auto* x : comp_nodes[b]) {
+                            comp_nodes[a].push_back(x);
+                            comp_of[x] = a;
+                        }
+                        for (auto* x : comp_srcs[b]) comp_srcs[a].push_back(x);
+                        for (int c : comp_contracts[b]) comp_contracts[a].push_back(c);
+                        std::sort(comp_nodes[a].begin(), comp_nodes[a].end(),
+                                  [](sg_node_s* x, sg_node_s* y) { return x->id < y->id; });
+                        comp_nodes.erase(b);
+                        comp_srcs.erase(b);
+                        comp_contracts.erase(b);
+                        roots.erase(roots.begin() + j);
+                        merged = true;
+                    }
+            }
+            roots_set = std::set<int>(roots.begin(), roots.end());
+        }
 
         plan->insts.clear();
         plan->steps.clear();
@@ -190,6 +271,11 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
             };
             for (auto* n : nodes) {
                 if (n->op == OPN_FILTER) {
+                    if (nspace >= MAX_SPACES && hmerge) {
+                        hmerge = false;
+                        resplit = true;
+                        break;
+                    }
                     if (nspace >= MAX_SPACES) return fail(ctx, SG_E_UNSUPPORTED, "more than 7 filters in one pass; add a split point");
                     space_filter[nspace] = n;
                     sp[n] = nspace++;
@@ -197,6 +283,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                     sp[n] = space_of(n->src[0]);
                 }
             }
+            if (resplit) break;
             // spaces whose ranks are needed
             std::set<int> scan_need;
             for (auto* n : nodes)
@@ -205,6 +292,11 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 const Contract& c = P->contracts[ci];
                 if ((c.check == SG_CHECK_FOR_ALL || c.check == SG_CHECK_EXISTS) && in_pass.count(c.node) && sp[c.node] != 0)
                     scan_need.insert(sp[c.node]);
+            }
+            if (scan_need.size() > 1 && hmerge) {
+                hmerge = false;
+                resplit = true;
+                break;
             }
             if (scan_need.size() > 1) {
                 // keep the first; split before the filter of every other one
@@ -447,6 +539,11 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 }
                 free_dead(i);
             }
+            if (too_many && hmerge) {
+                hmerge = false;
+                resplit = true;
+                break;
+            }
             if (too_many) return fail(ctx, SG_E_UNSUPPORTED, "chain too large for one pass (registers, sums, outputs); add a split point");
             if (ip.scan_space != 0) {
                 SgOp c{};
@@ -461,9 +558,14 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 ip.base_count_slot = c.aux;
                 prog.push_back(c);
             }
-            if ((int)prog.size() > MAX_INLINE_OPS) return fail(ctx, SG_E_UNSUPPORTED, "program longer than 48 operations; add a split point");
             int ndefer = 0;
             for (auto& o : prog) ndefer += (o.code == CHK_ALL || o.code == CHK_ANY) && o.sp != 0 && o.sp == ip.scan_space;
+            if (hmerge && ((int)prog.size() > MAX_INLINE_OPS || ndefer > MAX_DEFER || nslots > MAX_SLOTS)) {
+                hmerge = false;
+                resplit = true;
+                break;
+            }
+            if ((int)prog.size() > MAX_INLINE_OPS) return fail(ctx, SG_E_UNSUPPORTED, "program longer than 48 operations; add a split point");
             if (ndefer > MAX_DEFER) return fail(ctx, SG_E_UNSUPPORTED, "more than 2 quantified contracts on a compacted collection in one pass");
             if (nslots > MAX_SLOTS) return fail(ctx, SG_E_UNSUPPORTED, "more than 16 reductions/contracts in one pass");
             ip.result_index = (int)plan->insts.size();

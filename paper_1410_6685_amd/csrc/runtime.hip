@@ -383,6 +383,17 @@ sg_status sg_ctx_timing(sg_ctx ctx, const char* kernel, double* total_ms, int64_
     return SG_OK;
 }
 
+sg_status sg_ctx_last_launch(sg_ctx ctx, int32_t* grid, int32_t* block, int32_t* unroll, int32_t* substeps,
+                             int64_t* lds_bytes) {
+    if (!ctx) return SG_E_INVALID;
+    if (grid) *grid = ctx->last_grid;
+    if (block) *block = ctx->last_block;
+    if (unroll) *unroll = ctx->last_unroll;
+    if (substeps) *substeps = ctx->last_substeps;
+    if (lds_bytes) *lds_bytes = (int64_t)ctx->last_lds;
+    return SG_OK;
+}
+
 sg_status sg_ctx_timing_reset(sg_ctx ctx) {
     if (!ctx) return SG_E_INVALID;
     ctx->times.clear();

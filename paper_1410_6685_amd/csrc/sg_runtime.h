@@ -48,7 +48,8 @@ struct sg_ctx_s {
     int unroll = 2;
     int substeps = 8;
     uint32_t epoch = 0;  // host epoch of direct launches
-    int last_grid = 0;
+    int last_grid = 0, last_block = 0, last_unroll = 0, last_substeps = 0;  // last streaming launch
+    size_t last_lds = 0;
     bool timing = false;
     uint64_t next_id = 0;
     uint64_t generation = 0;  // bumped when a setting that changes plans changes
@@ -180,6 +181,8 @@ int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, 
 int inst_cemit(const InstPlan& ip);
 int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan);
 size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll);
+// dynamic LDS a streaming block may use (160 KiB per CU, less the kernel's static part)
+constexpr size_t kMaxDynamicLds = 152 * 1024;
 void retain(sg_node_s* n);
 void retain(sg_fn_s* f);
 void retain(sg_pred_s* p);

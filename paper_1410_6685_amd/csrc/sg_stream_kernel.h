@@ -211,6 +211,7 @@ struct Lds {
     uint32_t rcnt[64];                       // kept values per LDS region of the current tile
     uint32_t roff[64];                       // their exclusive prefix within the tile
     uint32_t dfirst[MAX_DEFER][64];          // first failing compacted rank per region
+    uint64_t ptotal;                         // kept values of the current tile
     int64_t excl;                            // the tile's exclusive prefix in the scan space
 };
 
@@ -237,12 +238,12 @@ __device__ __forceinline__ uint64_t tag_word(uint32_t epoch, uint32_t payload) {
 // given launch configuration.
 //
 // Compaction: each wave packs the kept values of its part of a sub-tile into its own LDS
-// region; at the end of the tile the block's count is published and one wave walks back
+// region; at the end of the tile the block publishes the tile's count, one wave walks back
 // over the published counts of earlier tiles (a decoupled look-back, 256 descriptors per
-// step) to the tile's exclusive prefix; then every wave copies its regions out, contiguous
-// and coalesced.  Waits only ever target lower-numbered tiles, which are processed in
-// increasing order by blocks that are all resident, so they end; every wait is bounded and
-// reports a device error instead of hanging.
+// step) to the tile's exclusive prefix, and every wave copies its regions out, contiguous
+// and coalesced.  Waits only ever target lower-numbered tiles, held by blocks that are all
+// resident (the grid is sized by occupancy), so they end; every wait is bounded and reports
+// a device error instead of hanging.
 //
 // Dynamic LDS layout (bytes): [lds_slots][blockDim] u64 | [lds_sums][blockDim] f64 |
 // [lds_cemit][substeps * waves][256U] u32.
@@ -388,10 +389,96 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         __syncthreads();
     };
 
+    // ---- compaction of the current tile ----
+    const uint64_t lb_epoch = (uint64_t)(epoch & 0x3FFFFFFFu) << 32;
+    constexpr uint64_t LB_AGG = 1ull << 62, LB_INC = 2ull << 62;
+
+    // wave 0: exclusive prefix of tile `pend` by a decoupled look-back; publishes its
+    // inclusive count and leaves the prefix (or -1 when none can be used) in L.excl
+    auto resolve = [&](int64_t pend) {
+        const uint64_t total = L.ptotal;
+        int64_t excl = 0;
+        if (pend != tile0) {
+            // descriptors at distance p + 1 = 1 + 64m + lane, nearest first
+            int64_t j = pend - 1;
+            for (uint32_t spins = 0;;) {
+                uint64_t d[LB_WINDOW];
+#pragma unroll
+                for (int m = 0; m < LB_WINDOW; ++m) {
+                    const int64_t idx = j - 64 * m - lane;
+                    d[m] = idx >= tile0 ? ld_relaxed(&A.lookback[idx]) : (LB_INC | lb_epoch);
+                }
+                int fi = 64 * LB_WINDOW;  // position of the nearest inclusive descriptor
+                bool wait = false;
+#pragma unroll
+                for (int m = 0; m < LB_WINDOW; ++m) {
+                    const bool valid = (d[m] & (0x3FFFFFFFull << 32)) == lb_epoch && (d[m] >> 62) != 0;
+                    const uint64_t incm = __ballot(valid && (d[m] >> 62) == 2);
+                    const uint64_t invm = __ballot(!valid);
+                    if (fi == 64 * LB_WINDOW) {
+                        const int f = incm ? __builtin_ctzll(incm) : 64;
+                        const uint64_t need = f >= 63 ? ~0ull : ((2ull << f) - 1ull);
+                        if (invm & need) wait = true;
+                        if (incm) fi = 64 * m + f;
+                    }
+                }
+                if (wait) {
+                    if (++spins > (1u << 22)) {
+                        if (lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
+                        excl = -1;  // no prefix: nothing of this tile is written
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                int64_t part = 0;
+#pragma unroll
+                for (int m = 0; m < LB_WINDOW; ++m)
+                    part += (64 * m + lane <= fi) ? (int64_t)(uint32_t)d[m] : 0;
+                excl += wave_sum_i64(part);
+                if (fi < 64 * LB_WINDOW) break;
+                j -= 64 * LB_WINDOW;
+            }
+            // after a timed-out wait the prefix is unknown; publishing the tile's own count
+            // keeps later tiles from waiting on it too (the launch reports the error)
+            if (lane == 0)
+                st_relaxed(&A.lookback[pend], LB_INC | lb_epoch | (uint64_t)(uint32_t)((excl >= 0 ? (uint64_t)excl : 0) + total));
+        }
+        if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
+        if (lane == 0) L.excl = excl;
+    };
+    // every wave: copy the tile's regions out at L.excl; deferred contract indices
+    auto copy_out = [&](int nreg) {
+        const int64_t excl = L.excl;
+        uint64_t dbest0 = 0, dbest1 = 0;
+        for (int rg = wave; rg < nreg && excl >= 0; rg += nwaves) {
+            const uint32_t cnt = L.rcnt[rg];
+            const int64_t ob = excl + L.roff[rg];
+            for (int ci = 0; ci < nce; ++ci) {
+                uint32_t* q = (uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1));
+                const uint32_t* st = stage + ((int64_t)ci * C * nwaves + rg) * RW;
+                for (uint32_t i = lane; i < cnt; i += 64) q[ob + i] = st[i];
+            }
+            for (int ci = 0; ci < nd; ++ci) {
+                const uint32_t f = L.dfirst[ci][rg];
+                if (f != 0xFFFFFFFFu) {
+                    const uint64_t e = ~(uint64_t)(ob + f);
+                    if (ci == 0) dbest0 = e > dbest0 ? e : dbest0;
+                    else dbest1 = e > dbest1 ? e : dbest1;
+                }
+            }
+        }
+        if (lane == 0) {
+            if (nd > 0 && dbest0) acc_max(d_slot0, dbest0);
+            if (nd > 1 && dbest1) acc_max(d_slot1, dbest1);
+        }
+    };
+
     uint32_t R[NREG][V];
     bool pf = false;  // R[0..nin) already hold the inputs of the next sub-tile
 
     for (int64_t t = blockIdx.x; t < A.total_tiles; t += gridDim.x) {
+        const int64_t t_next = t + (int64_t)gridDim.x;
         const int inst = INLINE ? 0 : (int)uload32(A.tile_inst + t);
         if (inst != cur || ntl == TILE_BUF) {
             if (cur >= 0) flush();
@@ -524,7 +611,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             {
                 int64_t nb = -1;
                 if (c + 1 < cend) nb = sub_base + sub_elems;
-                else if (INLINE && t + (int64_t)gridDim.x < A.total_tiles) nb = (t + (int64_t)gridDim.x - tile0) * C * sub_elems;
+                else if (INLINE && t_next < A.total_tiles) nb = (t_next - tile0) * C * sub_elems;
                 pf = nb >= 0 && nb + sub_elems <= n && (flags & 1);
                 if (pf) {
                     const int64_t ne0 = nb + (int64_t)wave * RW + lane * 4;
@@ -546,7 +633,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             }
         }
 
-        // ---------------- tile end: compaction prefix and copy-out -----------------------------
+        // ---------------- tile end: publish the tile's count, resolve its prefix, copy out -----
         if (SG_GEN_HAS_SCAN && scan_space != 0) {
             __syncthreads();
             const int nreg = cend * nwaves;  // regions written in this tile (at most 64)
@@ -560,85 +647,14 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 }
                 L.roff[lane] = incl - cnt;
                 const uint64_t total = (uint64_t)__shfl(incl, 63);
-                const uint64_t ep = (uint64_t)(epoch & 0x3FFFFFFFu) << 32;
-                const uint64_t AGG = 1ull << 62, INC = 2ull << 62;
-                int64_t excl = 0;
-                if (t == tile0) {
-                    if (lane == 0) st_relaxed(&A.lookback[t], INC | ep | total);
-                } else {
-                    if (lane == 0) st_relaxed(&A.lookback[t], AGG | ep | total);
-                    // descriptors at distance p + 1 = 1 + 64m + lane, nearest first
-                    int64_t j = t - 1;
-                    for (uint32_t spins = 0;;) {
-                        uint64_t d[LB_WINDOW];
-#pragma unroll
-                        for (int m = 0; m < LB_WINDOW; ++m) {
-                            const int64_t idx = j - 64 * m - lane;
-                            d[m] = idx >= tile0 ? ld_relaxed(&A.lookback[idx]) : (INC | ep);
-                        }
-                        int fi = 64 * LB_WINDOW;  // position of the nearest inclusive descriptor
-                        bool wait = false;
-#pragma unroll
-                        for (int m = 0; m < LB_WINDOW; ++m) {
-                            const bool valid = (d[m] & (0x3FFFFFFFull << 32)) == ep && (d[m] >> 62) != 0;
-                            const uint64_t incm = __ballot(valid && (d[m] >> 62) == 2);
-                            const uint64_t invm = __ballot(!valid);
-                            if (fi == 64 * LB_WINDOW) {
-                                const int f = incm ? __builtin_ctzll(incm) : 64;
-                                const uint64_t need = f >= 63 ? ~0ull : ((2ull << f) - 1ull);
-                                if (invm & need) wait = true;
-                                if (incm) fi = 64 * m + f;
-                            }
-                        }
-                        if (wait) {
-                            if (++spins > (1u << 22)) {
-                                if (lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
-                                excl = -1;  // no prefix: nothing of this tile is written
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                            continue;
-                        }
-                        int64_t part = 0;
-#pragma unroll
-                        for (int m = 0; m < LB_WINDOW; ++m)
-                            part += (64 * m + lane <= fi) ? (int64_t)(uint32_t)d[m] : 0;
-                        excl += wave_sum_i64(part);
-                        if (fi < 64 * LB_WINDOW) break;
-                        j -= 64 * LB_WINDOW;
-                    }
-                    // after a timed-out wait the prefix is unknown; publishing the tile's own count
-                    // keeps later tiles from waiting on it too (the launch reports the error)
-                    if (lane == 0)
-                        st_relaxed(&A.lookback[t], INC | ep | (uint64_t)(uint32_t)((excl >= 0 ? (uint64_t)excl : 0) + total));
+                if (lane == 0) {
+                    L.ptotal = total;
+                    st_relaxed(&A.lookback[t], (t == tile0 ? LB_INC : LB_AGG) | lb_epoch | total);
                 }
-                if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
-                if (lane == 0) L.excl = excl;
+                resolve(t);
             }
             __syncthreads();
-            const int64_t excl = L.excl;
-            uint64_t dbest0 = 0, dbest1 = 0;
-            for (int rg = wave; rg < nreg && excl >= 0; rg += nwaves) {
-                const uint32_t cnt = L.rcnt[rg];
-                const int64_t ob = excl + L.roff[rg];
-                for (int ci = 0; ci < nce; ++ci) {
-                    uint32_t* q = (uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1));
-                    const uint32_t* st = stage + ((int64_t)ci * C * nwaves + rg) * RW;
-                    for (uint32_t i = lane; i < cnt; i += 64) q[ob + i] = st[i];
-                }
-                for (int ci = 0; ci < nd; ++ci) {
-                    const uint32_t f = L.dfirst[ci][rg];
-                    if (f != 0xFFFFFFFFu) {
-                        const uint64_t e = ~(uint64_t)(ob + f);
-                        if (ci == 0) dbest0 = e > dbest0 ? e : dbest0;
-                        else dbest1 = e > dbest1 ? e : dbest1;
-                    }
-                }
-            }
-            if (lane == 0) {
-                if (nd > 0 && dbest0) acc_max(d_slot0, dbest0);
-                if (nd > 1 && dbest1) acc_max(d_slot1, dbest1);
-            }
+            copy_out(nreg);
         }
         // tile end: its sums, added over the lanes and then the waves in a fixed order, are
         // buffered for publication

@@ -269,11 +269,12 @@ sg_status sg_select_plan(sg_mlp m, sg_program p, const sg_plan* plans, int32_t n
     float* Xd = (float*)buf;
     float* Yd = Xd + X.size();
     std::vector<float> Y(n);
-    SG_HIP(ctx, hipMemcpyAsync(Xd, X.data(), X.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-    sg_status st = sg_mlp_predict(m, Xd, n, Yd);
+    hipError_t e = hipMemcpyAsync(Xd, X.data(), X.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    sg_status st = e == hipSuccess ? sg_mlp_predict(m, Xd, n, Yd) : hip_fail(ctx, e, "select_plan: upload");
     if (st == SG_OK) {
-        SG_HIP(ctx, hipMemcpyAsync(Y.data(), Yd, (size_t)n * 4, hipMemcpyDeviceToHost, ctx->stream));
-        SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        e = hipMemcpyAsync(Y.data(), Yd, (size_t)n * 4, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = hip_fail(ctx, e, "select_plan: read-back");
     }
     dev_free(ctx, buf);
     if (st != SG_OK) return st;

@@ -73,3 +73,26 @@ def test_batch_with_launch_configs(sg, ctx):
             nv = len(sp["contracts"])
             compare(sp, b, statuses[i], verdicts[k:k + nv], oracle.evaluate(sp, inp))
             k += nv
+
+
+def test_cfg4_full_size_sampled(sg, ctx):
+    """The 10,000-instance workload in the launch configuration the benchmark tunes for:
+    sampled instances (shortest, longest, poisoned-free random picks) against the oracle."""
+    import bench
+    import workloads as W
+    say("cfg4 full build")
+    specs, builts, _, _, _ = bench.cfg4_build(ctx, 10_000)
+    for block, unroll in [(256, 4), (256, 1)]:
+        say("cfg4 full run", block, unroll)
+        ctx.set_launch(block, unroll)
+        try:
+            batch = sg.Batch(ctx, [b.program for b in builts], use_graph=True)
+            statuses, verdicts = batch.run()
+        finally:
+            ctx.set_launch(256, 2)
+        lengths = np.array([sp["inputs"][0]["n"] for sp in specs])
+        pick = sorted(set([int(np.argmin(lengths)), int(np.argmax(lengths))] +
+                          list(np.random.Generator(np.random.PCG64(5)).choice(len(specs), 10, replace=False))))
+        for i in pick:
+            ref = oracle.evaluate(specs[i], W.cfg4_instance_inputs(specs[i], 1000 + i))
+            compare(specs[i], builts[i], statuses[i], verdicts[i:i + 1], ref)

@@ -98,3 +98,57 @@ def test_features_and_selector(sg, ctx):
     net.set_norm(mean, scale, f.min(axis=0) + 100.0, f.max(axis=0) + 100.0)  # everything out of range
     _, _, fb = net.select(built.program, PLANS, margin=0.0)
     assert fb
+
+
+def selector_inputs(spec, seed):
+    out = {}
+    for k, inp in enumerate(spec["inputs"]):
+        if inp["dtype"] == "f32":
+            out[inp["name"]] = W.uniform_f32(inp["n"], seed * 4 + k)
+        else:
+            out[inp["name"]] = W.uniform_i32(inp["n"], seed * 4 + k, -50000, 50000)
+    return out
+
+
+@pytest.mark.parametrize("seed", [51 * 100003 + 2, 51 * 100003 + 61, 7, 8, 9, 10])
+def test_split_plans_on_selector_chains(sg, ctx, seed):
+    """Every candidate plan of the selector (fusion splits included) plans and gives the
+    oracle's results; among them chains whose split output feeds a pass that also reads an
+    input of the split's own pass."""
+    from paper_1410_6685_amd import selector
+    spec = W.selector_chain_spec(30_011, seed)
+    inp = selector_inputs(spec, seed)
+    built = sg.build_spec(ctx, spec, to_dev(inp))
+    ref = oracle.evaluate(spec, inp)
+    plans = selector.candidate_plans(built.program) + [(256, 2, 8, k) for k in range(built.program.split_candidates())]
+    for plan in plans:
+        say("selector chain", seed, plan)
+        built.program.set_plan(plan)
+        status, verdicts = built.program.execute()
+        compare(spec, built, status, verdicts, ref)
+
+
+def test_passes_share_inputs(sg, ctx):
+    """Chains reading a common input, and chains over inputs of one length, run as one pass;
+    a chain that reads another's written output does not join it."""
+    n = 50_000
+    x, y, k = W.uniform_f32(n, 1), W.uniform_f32(n, 2), np.sort(W.uniform_i32(n, 3))
+    spec = {"inputs": [{"name": "x", "dtype": "f32", "n": n}, {"name": "y", "dtype": "f32", "n": n},
+                       {"name": "k", "dtype": "i32", "n": n}],
+            "nodes": [{"name": "a", "op": "map", "src": "x", "fn": ["affine", 2.0, 1.0]},
+                      {"name": "sa", "op": "reduce", "src": "a", "red": "sum"},
+                      {"name": "b", "op": "zip", "a": "x", "b": "y", "binop": "mul"},
+                      {"name": "mb", "op": "reduce", "src": "b", "red": "max"}],
+            "contracts": [{"kind": "require", "check": "for_all", "node": "x", "pred": ["isfinite"]},
+                          {"kind": "ensure", "check": "sorted", "node": "k"}],
+            "outputs": ["sa", "mb"]}
+    inp = {"x": x, "y": y, "k": k}
+    built = sg.build_spec(ctx, spec, to_dev(inp))
+    assert built.program.features((256, 2, 8, -1))[21] == 1  # one pass for everything
+    status, verdicts = built.program.execute()
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
+    # a split at `a`: the pass summing `a` reads it from memory, and x's other readers stay put
+    built.program.set_plan((256, 2, 8, 0))
+    assert built.program.features((256, 2, 8, 0))[21] >= 2
+    status, verdicts = built.program.execute()
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))

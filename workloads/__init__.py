@@ -242,6 +242,62 @@ def cfg4_instance_inputs(spec: dict, seed: int) -> dict:
     return out
 
 
+# ---- cfg5: chains for the plan selector's timing dataset ----------------------------------------
+
+SELECTOR_F32_FNS = (["affine"], ["sqrt_abs"], ["exp_neg_sq"], ["square"], ["neg"], ["abs"])
+SELECTOR_I32_FNS = (["affine"], ["square"], ["neg"], ["abs"])
+
+
+def selector_lengths(count: int, seed: int, lo_exp: float = 10.0, hi_exp: float = 28.0) -> np.ndarray:
+    u = rng(seed).uniform(lo_exp, hi_exp, size=count)
+    return np.floor(np.exp2(u)).astype(np.int64)
+
+
+def selector_chain_spec(n: int, seed: int) -> dict:
+    """A seeded chain for the plan selector: depth 1-16 element-wise steps over x (float32 or
+    int32), zips with a second input y before any filter, up to two filters, a terminal
+    sum / max / count, and with probability 1/2 one for_all contract."""
+    g = rng(seed)
+    dt = F32 if g.integers(0, 4) > 0 else I32
+    depth = int(g.integers(1, 16, endpoint=True))
+    inputs = [{"name": "x", "dtype": dt, "n": n}]
+    nodes, cur, has_y, nfilter, last_unfiltered = [], "x", False, 0, "x"
+    fns = SELECTOR_F32_FNS if dt == F32 else SELECTOR_I32_FNS
+    for d in range(depth - 1):
+        kinds = ["map", "map", "map"] + (["zip"] if nfilter == 0 else []) + (["filter"] if nfilter < 2 else [])
+        kind = kinds[int(g.integers(0, len(kinds)))]
+        name = f"n{d}"
+        if kind == "map":
+            fn = list(fns[int(g.integers(0, len(fns)))])
+            if fn[0] == "affine":
+                if dt == F32:
+                    fn = ["affine", f32(g.uniform(-1.5, 1.5)), f32(g.uniform(-1, 1))]
+                else:
+                    fn = ["affine", int(g.integers(-3, 4)), int(g.integers(-100, 101))]
+            nodes.append({"name": name, "op": "map", "src": cur, "fn": fn})
+        elif kind == "zip":
+            if not has_y:
+                inputs.append({"name": "y", "dtype": dt, "n": n})
+                has_y = True
+            nodes.append({"name": name, "op": "zip", "a": cur, "b": "y",
+                          "binop": ["add", "sub", "mul"][int(g.integers(0, 3))]})
+        else:
+            t = f32(g.uniform(-0.5, 0.5)) if dt == F32 else int(g.integers(-1000, 1000))
+            nodes.append({"name": name, "op": "filter", "src": cur,
+                          "pred": ["cmp", ["gt", "lt", "ge"][int(g.integers(0, 3))], t]})
+            nfilter += 1
+        cur = name
+        if nfilter == 0:
+            last_unfiltered = name
+    red = ["sum", "max", "count"][int(g.integers(0, 3))]
+    nodes.append({"name": "r", "op": "reduce", "src": cur, "red": red})
+    contracts = []
+    if g.integers(0, 2) == 0:
+        pred = ["isfinite"] if dt == F32 else ["in_range", -(2 ** 31), 2 ** 31 - 1]
+        contracts.append({"kind": "require", "check": "for_all", "node": last_unfiltered, "pred": pred})
+    return {"inputs": inputs, "nodes": nodes, "contracts": contracts, "outputs": ["r"]}
+
+
 def spec_copy(spec: dict) -> dict:
     return copy.deepcopy(spec)
 
