@@ -199,7 +199,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 for (auto* x : all) {
                     inputs_only &= x->op == OPN_INPUT;
                     if (x->n != s0->n) return false;
-                    const bool cx = x->op == OPN_FILTER, c0 = s0->op == OPN_FILTER;
+                    const bool cx = x->space != 0, c0 = s0->space != 0;  // compacted collections
                     if (cx != c0 || (cx && x != s0 && x->space != s0->space)) return false;
                 }
                 if (!shared && !inputs_only) return false;
@@ -252,12 +252,12 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
             sg_node_s* s0 = srcs[0];
             for (auto* s : srcs) {
                 if (s->n != s0->n) return fail(ctx, SG_E_SHAPE, "sources of one pass differ in length");
-                const bool cs = s->op == OPN_FILTER, c0 = s0->op == OPN_FILTER;
+                const bool cs = s->space != 0, c0 = s0->space != 0;  // compacted collections
                 if (cs != c0 || (cs && s != s0 && s->space != s0->space))
                     return fail(ctx, SG_E_SHAPE, "sources of one pass lie in different index spaces");
             }
             ip.n = s0->n;
-            ip.n_src = s0->op == OPN_FILTER ? s0 : nullptr;
+            ip.n_src = s0->space != 0 ? s0 : nullptr;  // count of a compacted source: on the device
 
             // index spaces: 0 = the sources' space; each filter in the pass opens a new one
             std::map<sg_node_s*, int> sp;
