@@ -25,9 +25,14 @@ HBM_PEAK_GBS = 8000.0
 N_DEFAULT = 1 << 26
 
 
+KERNEL_SOURCES = ("sg_stream_kernel.h", "sg_stream_ops.inc", "sg_kernels.h", "sg_exp.h", "sg_exp_table.h", "jit.hip")
+
+
 def kernel_hash() -> str:
+    """Hash of the streaming kernel's sources (a committed counter profile is used only if it
+    was taken on this code)."""
     h = hashlib.sha256()
-    for f in ("stream.hip", "sg_kernels.h", "sg_exp.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1410_6685_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -45,7 +50,7 @@ def measured_traffic(per_launch_algo_bytes: float):
         return None
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("bytes_per_launch")
+    return round(d["fetch_kib"] * 1024 * d["fetch_scale"] + d["write_kib"] * 1024 * d["write_scale"], 0)
 
 
 def cpu_baseline(n_sample: int) -> dict:
@@ -68,6 +73,58 @@ def cpu_baseline(n_sample: int) -> dict:
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---- matrix product with its product postcondition -------------------------------------------------
+
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def run_cfg3(ctx, steps: int, warmup: int, n: int = 4096) -> dict:
+    """C = A B on FP32 MFMA with the Freivalds ensure (4 probe vectors, float64 check)."""
+    import torch
+
+    import paper_1410_6685_amd as sg
+    import workloads as W
+
+    inp = W.cfg3_inputs(n)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    built = sg.build_spec(ctx, W.cfg3_spec(n), dev)
+    ctx.set_mode("pre_post")
+    for _ in range(warmup):
+        built.program.execute()
+    ctx.set_timing(True)
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        status, verdicts = built.program.execute()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ctx.set_timing(False)
+    g_ms, g_n = ctx.timing("gemm")
+    c_ms, c_n = ctx.timing("product_check")
+    g = g_ms / max(g_n, 1)
+    c = c_ms / max(c_n, 1)
+    tflops = 2.0 * n ** 3 / (g * 1e-3) / 1e12
+    check_bytes = 4.0 * 3 * n * n
+    return {"n": n, "status": status, "product_holds": int(verdicts[0].holds),
+            "max_err_over_bound": verdicts[0].measure, "gemm_ms": round(g, 4), "gemm_TFLOPs": round(tflops, 2),
+            "mfma_fp32_frac": round(tflops / MFMA_FP32_PEAK_TFLOPS, 4), "check_ms": round(c, 4),
+            "check_GBs": round(check_bytes / (c * 1e-3) / 1e9, 1),
+            "check_overhead_pct": round(100.0 * c / g, 2), "ms_per_step": round(wall * 1e3, 4)}
+
+
+def calibrate_copy(nbytes: int = 1 << 28, reps: int = 5) -> None:
+    """A plain device copy of known size, to scale the HBM byte counters of a profile."""
+    import torch
+
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
 
 
 # ---- batched uneven instances -------------------------------------------------------------------
@@ -242,6 +299,8 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a 256 MiB device copy (profiling aid)")
+    ap.add_argument("--no-cfg3", action="store_true", help="skip the matrix-product workload")
     ap.add_argument("--cfg4-instances", type=int, default=10_000, help="0 skips the batched workload")
     ap.add_argument("--cfg5-train", type=int, default=1500, help="training chains (0 skips the selector)")
     ap.add_argument("--cfg5-test", type=int, default=500)
@@ -252,6 +311,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is described "
               "in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import numpy as np
     import torch
@@ -273,20 +336,21 @@ def main():
     built = sg.build_spec(ctx, spec, dev)
     prog = built.program
 
-    def run_steps(k):
+    def run_steps(k, p):
         for _ in range(k):
-            st, _ = prog.execute()
+            st, _ = p.execute()
             if st not in ("ok", "post_violated"):
                 raise RuntimeError(f"unexpected status {st}")
 
-    def timed(mode: str, steps: int, warmup: int):
+    def timed(mode: str, steps: int, warmup: int, p=None):
+        p = p or prog
         ctx.set_mode(mode)
-        run_steps(warmup)
+        run_steps(warmup, p)
         ctx.set_timing(True)
         ctx.timing_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        run_steps(steps)
+        run_steps(steps, p)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ctx.set_timing(False)
@@ -296,6 +360,7 @@ def main():
     print("[bench] timing pre_post", file=sys.stderr, flush=True)
     wall, k_ms, k_launches = timed("pre_post", args.steps, args.warmup)
     status, verdicts = prog.execute()
+    shape = dict(zip(("grid", "block", "unroll", "substeps", "lds_bytes"), ctx.last_launch()))
     count = built["c"].scalar()[1]
     algo_bytes = 12.0 * n + 4.0 * count
     ms_per_step = wall * 1e3 / args.steps
@@ -309,8 +374,19 @@ def main():
     if not args.no_extras:
         print("[bench] timing off (contract overhead)", file=sys.stderr, flush=True)
         wall_off, k_ms_off, _ = timed("off", args.steps, args.warmup)
+        # whole workload: the sortedness postcondition reads the 256 MiB keys array, which
+        # nothing else reads, so "off" skips half as much data again
         extras["contract_overhead_pct"] = round(100.0 * (wall - wall_off) / wall_off, 2)
         extras["contract_overhead_kernel_pct"] = round(100.0 * (k_ms - k_ms_off) / k_ms_off, 2)
+        # the chain's own range contracts (require x, y finite; ensure every kept value > 0.1),
+        # the ratio of the paper's contract-overhead table
+        chain = sg.build_spec(ctx, W.cfg2_spec(n, with_keys=False), {"x": dev["x"], "y": dev["y"]})
+        print("[bench] timing chain contracts on/off", file=sys.stderr, flush=True)
+        _, kc_on, _ = timed("pre_post", args.steps, args.warmup, chain.program)
+        _, kc_off, _ = timed("off", args.steps, args.warmup, chain.program)
+        extras["contract_overhead_chain_kernel_pct"] = round(100.0 * (kc_on - kc_off) / kc_off, 2)
+        extras["chain_only_kernel_ms"] = round(kc_on / args.steps, 5)
+        del chain
         ctx.set_fusion(False)
         print("[bench] timing unfused", file=sys.stderr, flush=True)
         wall_unf, _, _ = timed("pre_post", max(3, args.steps // 4), 1)
@@ -323,8 +399,12 @@ def main():
     extras["sorted_first_violation"] = int(verdicts[3].first_index)
     extras["stream_launches_per_step"] = launches_per_step
     extras["stream_kernel_ms_per_step"] = round(k_ms / args.steps, 5)
-    extras["launch_shape"] = dict(zip(("grid", "block", "unroll", "substeps", "lds_bytes"), ctx.last_launch()))
+    extras["launch_shape"] = shape
     del built, prog, dev
+    if not args.no_extras and not args.no_cfg3:
+        log("cfg3: matrix product with product ensure")
+        extras["cfg3_matmul"] = run_cfg3(ctx, max(3, args.steps // 2), 2)
+        torch.cuda.empty_cache()
     if not args.no_extras and args.cfg4_instances > 0:
         ctx.set_specialize(False)
         extras["cfg4_batched"] = run_cfg4(ctx, args.cfg4_instances, args.steps, args.warmup)

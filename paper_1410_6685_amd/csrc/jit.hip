@@ -59,7 +59,7 @@ std::string unit_source(const InstPlan& ip, int unroll, int lb) {
     std::snprintf(buf, sizeof(buf),
                   "#define SG_PROGRAM_INC \"sg_program_gen.inc\"\n#define SG_GEN_HAS_SCAN %d\n#define SG_GEN_NIN %d\n"
                   "#include \"sg_stream_kernel.h\"\n"
-                  "// instantiated through the name expression sg::stream_kernel<%d, true, %d>\n",
+                  "// instantiated through the name expression sg::stream_kernel<%d, true, %d, 1>\n",
                   ip.scan_space != 0 ? 1 : 0, (int)ip.sources.size(), unroll, lb);
     return buf;
 }
@@ -89,7 +89,7 @@ sg_status jit_kernel(sg_ctx_s* ctx, const InstPlan& ip, int unroll, int block, v
                             hdr_name.data()) != HIPRTC_SUCCESS)
         return fail(ctx, SG_E_DEVICE, "hiprtc: create program");
     char expr[96];
-    std::snprintf(expr, sizeof(expr), "&sg::stream_kernel<%d, true, %d>", unroll, lb);
+    std::snprintf(expr, sizeof(expr), "&sg::stream_kernel<%d, true, %d, 1>", unroll, lb);
     (void)hiprtcAddNameExpression(rp, expr);
     char arch[64];
     std::snprintf(arch, sizeof(arch), "--offload-arch=%s", ctx->arch.c_str());

@@ -250,7 +250,8 @@ __device__ __forceinline__ uint64_t tag_word(uint32_t epoch, uint32_t payload) {
 
 constexpr int LB_WINDOW = 4;  // look-back descriptors per lane per step
 
-template <int U, bool INLINE, int LB>
+// SPEC = 1 marks a kernel compiled at run time for one program (its own symbol in traces).
+template <int U, bool INLINE, int LB, int SPEC = 0>
 __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const StreamArgs A) {
     constexpr int V = 4 * U;
     constexpr int RW = 256 * U;  // elements of a wave's part of a sub-tile
