@@ -63,6 +63,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     std::vector<SgOp> ops;
     std::vector<int32_t> tile_inst;
     int max_slots = 0, max_sums = 0, max_cemit = 0;
+    bool any_scan = false;
     for (int i = 0; i < n; ++i) {
         sg_program_s* P = progs[i];
         if (!P || P->ctx != ctx) { batch_free(b); return fail(ctx, SG_E_INVALID, "batch_create: bad program"); }
@@ -80,10 +81,11 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
         max_slots = std::max(max_slots, (int)ip.slot_kind.size());
         max_sums = std::max(max_sums, ip.nsum);
         max_cemit = std::max(max_cemit, inst_cemit(ip));
+        any_scan |= ip.scan_space != 0;
     }
     // the per-lane accumulators and staging buffers of every instance must fit in LDS
     for (;; b->unroll /= 2) {
-        b->lds = stream_lds_bytes(max_slots, max_sums, max_cemit, b->substeps, b->block, b->unroll);
+        b->lds = stream_lds_bytes(max_slots, max_sums, max_cemit, b->substeps, b->block, b->unroll, 1);
         if (b->lds <= kMaxDynamicLds || b->unroll == 1) break;
     }
     if (b->lds > kMaxDynamicLds) {
@@ -134,7 +136,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     a.lds_slots = max_slots;
     a.lds_sums = max_sums;
     a.lds_cemit = max_cemit;
-    b->grid = stream_grid(ctx, b->total_tiles, false, b->unroll, b->block, b->lds);
+    b->grid = stream_grid(ctx, b->total_tiles, false, b->unroll, b->block, b->lds, any_scan);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) { batch_free(b); return fail(ctx, SG_E_DEVICE, "batch sync"); }
     if (use_graph) {
         // the graph holds only the kernel node (no memset nodes): the kernel leaves its

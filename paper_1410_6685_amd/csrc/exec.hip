@@ -55,17 +55,27 @@ float key_to_float(int32_t k) {
 
 }  // namespace
 
-int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes) {
+// Blocks per CU a pass may count on being resident together.  A pass that compacts waits on
+// other blocks' tiles, so all of its grid must be resident: the runtime's occupancy figure
+// has been seen to admit one block per CU too many (when LDS is filled exactly, and when the
+// scalar registers bound a small kernel at 7 waves per SIMD), so such passes keep one block
+// per CU in reserve.
+int coresident_blocks(int occupancy, bool waits_on_others) {
+    if (!waits_on_others) return std::max(occupancy, 1);
+    return std::max(occupancy >= 3 ? occupancy - 1 : occupancy, 1);
+}
+
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes, bool waits) {
     auto key = std::make_tuple(unroll * (inl ? 1 : -1), block, lds_bytes);
     auto it = ctx->occupancy.find(key);
     int nb;
     if (it != ctx->occupancy.end()) {
         nb = it->second;
     } else {
-        nb = sg_stream_occupancy(unroll, inl, block, lds_bytes);
+        nb = std::min(sg_stream_occupancy(unroll, inl, block, lds_bytes), lds_blocks_per_cu(lds_bytes));
         ctx->occupancy[key] = nb;
     }
-    const int64_t cap = (int64_t)nb * ctx->num_cu;
+    const int64_t cap = (int64_t)coresident_blocks(nb, waits) * ctx->num_cu;
     return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cap));
 }
 
@@ -75,17 +85,24 @@ int inst_cemit(const InstPlan& ip) {
     return k;
 }
 
-size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll) {
-    return (size_t)(slots + sums) * block * 8 + (size_t)cemit * C * block * 4 * unroll * 4;
+size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll, int nbuf) {
+    return (size_t)(slots + sums) * block * 8 + (size_t)nbuf * cemit * C * block * 4 * unroll * 4;
 }
 
 // A pass with a scan space keeps one LDS region per wave and sub-tile of a tile (at most
 // 64), and its staged values in at most 64 KiB, so that two blocks fit on a CU.
-int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan) {
+int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan, int nbuf) {
     if (!scan) return C;
     int c = std::min(C, 64 / (block / 64));
-    while (c > 1 && stream_lds_bytes(slots, sums, cemit, c, block, unroll) > 65536) --c;
+    while (c > 1 && stream_lds_bytes(slots, sums, cemit, c, block, unroll, nbuf) > 65536) --c;
     return std::max(c, 1);
+}
+
+// Resident blocks per CU allowed by LDS, with a margin: the runtime's occupancy figure has
+// been seen to admit one block too many when a grid fills the LDS exactly, and the
+// compaction's waits need every block of the grid resident.
+int lds_blocks_per_cu(size_t dyn_lds) {
+    return (int)std::max<size_t>(1, (kLdsPerCu - kLdsReserve) / (dyn_lds + kStaticLdsBound));
 }
 
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n) {
@@ -270,8 +287,8 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         Geo& g = geo[i];
         const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
         for (g.U = unroll;; g.U /= 2) {
-            g.C = stream_substeps(C0, block, g.U, ns, ip.nsum, ce, ip.scan_space != 0);
-            g.lds = stream_lds_bytes(ns, ip.nsum, ce, g.C, block, g.U);
+            g.C = stream_substeps(C0, block, g.U, ns, ip.nsum, ce, ip.scan_space != 0, 2);
+            g.lds = stream_lds_bytes(ns, ip.nsum, ce, g.C, block, g.U, 2);
             if (g.lds <= kMaxDynamicLds || g.U == 1) break;
         }
         if (g.lds > kMaxDynamicLds)
@@ -283,11 +300,12 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         const int64_t sub_elems = (int64_t)block * 4 * g.U;
         const int64_t nsub = std::max<int64_t>(1, (ip.n + sub_elems - 1) / sub_elems);
         g.ntiles = (nsub + g.C - 1) / g.C;
+        const bool waits = ip.scan_space != 0;
         if (jks[i]) {
-            const int64_t cap = (int64_t)jit_occupancy(jks[i], block, g.lds) * ctx->num_cu;
-            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, cap));
+            const int occ = coresident_blocks(std::min(jit_occupancy(jks[i], block, g.lds), lds_blocks_per_cu(g.lds)), waits);
+            g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, (int64_t)occ * ctx->num_cu));
         } else {
-            g.grid = stream_grid(ctx, g.ntiles, true, g.U, block, g.lds);
+            g.grid = stream_grid(ctx, g.ntiles, true, g.U, block, g.lds, waits);
         }
         max_tiles = std::max(max_tiles, g.ntiles);
     }
@@ -296,7 +314,8 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     const int64_t nres = (int64_t)plan.insts.size() + nprod;
     for (auto& ip : plan.insts)
         if (ip.result_index < 0 || ip.result_index >= nres) return fail(ctx, SG_E_UNSUPPORTED, "plan result index out of range");
-    sg_status st = ensure_scratch(ctx, max_tiles, max_tiles, nres);
+    // look-back words: one per tile, then one per round (round bases)
+    sg_status st = ensure_scratch(ctx, max_tiles, 2 * max_tiles + 2, nres);
     if (st != SG_OK) return st;
     for (auto* m : plan.mats)
         if ((st = alloc_output(ctx, m)) != SG_OK) return st;
@@ -387,12 +406,16 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         }
     }
     for (int64_t i = 0; i < nres; ++i) {
-        if (ctx->host_results[i].err) {
+        if (const uint32_t err = ctx->host_results[i].err) {
             // reset the state the kernels keep between launches, then report
             (void)hipMemsetAsync(S.base, 0, S.bytes, ctx->stream);
             (void)hipStreamSynchronize(ctx->stream);
             ctx->epoch = 0;
-            return fail(ctx, SG_E_DEVICE, "streaming kernel reported a device-side failure (a bounded wait timed out)");
+            return fail(ctx, SG_E_DEVICE,
+                        (err & ERR_LOOKBACK_TIMEOUT) && (err & ERR_FINALIZE_TIMEOUT)
+                            ? "streaming kernel: bounded waits timed out (compaction prefix and result finalization)"
+                        : (err & ERR_LOOKBACK_TIMEOUT) ? "streaming kernel: a bounded wait for the compaction prefix timed out"
+                                                        : "streaming kernel: the bounded wait of the result finalization timed out");
         }
     }
 

@@ -175,12 +175,17 @@ void fill_inst(const InstPlan& ip, sg::InstDesc& d, int64_t tile0, int64_t ntile
 void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_values);
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n);
 sg_status assemble_verdicts(sg_program_s* P, const sg::InstResult* results, std::vector<sg_verdict>& V);
-int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes);
+int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes, bool waits);
+int coresident_blocks(int occupancy, bool waits_on_others);
 // Launch shape of a pass: sub-tiles per tile (clamped when values are staged for
 // compaction) and the dynamic LDS bytes of its per-lane accumulators and staging regions.
 int inst_cemit(const InstPlan& ip);
-int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan);
-size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll);
+int stream_substeps(int C, int block, int unroll, int slots, int sums, int cemit, bool scan, int nbuf);
+size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int unroll, int nbuf);
+int lds_blocks_per_cu(size_t dyn_lds);
+constexpr size_t kLdsPerCu = 160 * 1024;      // LDS of a gfx950 CU
+constexpr size_t kLdsReserve = 2 * 1024;      // margin kept free when sizing a resident grid
+constexpr size_t kStaticLdsBound = 8 * 1024;  // the streaming kernel's static LDS (checked there)
 // dynamic LDS a streaming block may use (160 KiB per CU, less the kernel's static part)
 constexpr size_t kMaxDynamicLds = 152 * 1024;
 void retain(sg_node_s* n);

@@ -111,6 +111,16 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
     return v;
 }
 
+// Block barrier that orders LDS only: global loads in flight (the next sub-tile's inputs)
+// stay in flight across it, where __syncthreads() would first wait for every one of them.
+// Used wherever the block exchanges only LDS data; global results other blocks read are
+// ordered by their own atomics and waits.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -208,12 +218,14 @@ struct Lds {
     double tsum[TILE_BUF][MAX_SUMS];         // sums of tiles not yet published
     int64_t tile[TILE_BUF];
     double fin[MAX_WAVES][MAX_SUMS];
-    uint32_t rcnt[64];                       // kept values per LDS region of the current tile
-    uint32_t roff[64];                       // their exclusive prefix within the tile
-    uint32_t dfirst[MAX_DEFER][64];          // first failing compacted rank per region
-    uint64_t ptotal;                         // kept values of the current tile
-    int64_t excl;                            // the tile's exclusive prefix in the scan space
+    uint32_t rcnt[2][64];                    // kept values per LDS region, per staging buffer
+    uint32_t roff[2][64];                    // their exclusive prefix within the tile
+    uint32_t dfirst[2][MAX_DEFER][64];       // first failing compacted rank per region
+    uint64_t ptotal[2];                      // kept values of the staged tile
+    int64_t excl;                            // exclusive prefix of the tile being copied out
 };
+
+static_assert(sizeof(Lds) <= 8 * 1024, "static LDS bound assumed by the host's grid sizing");
 
 __device__ __forceinline__ uint64_t tag_word(uint32_t epoch, uint32_t payload) {
     return ((uint64_t)epoch << 32) | payload;
@@ -231,24 +243,31 @@ __device__ __forceinline__ uint64_t tag_word(uint32_t epoch, uint32_t payload) {
 // Accumulators are per lane, in LDS (dynamic part): exact slots (counts, int sums, min/max
 // keys, first indices) are combined over the block once per instance and flushed to device
 // accumulators spread over `spread` copies; float64 sums are combined once per tile in a
-// fixed order (lanes, then waves) and published in epoch-tagged 64-bit words; the block
-// holding an instance's last tile waits until every tile word of the instance carries this
-// launch's epoch (which also proves every contributing block has flushed), adds the sums
-// in tile order and writes the result.  Sums are thus identical from run to run for a
-// given launch configuration.
+// fixed order (lanes, then waves).  A single-program pass keeps one running sum per block
+// (its tiles in order) and publishes it once, in epoch-tagged 64-bit words indexed by block;
+// a batched launch publishes per tile.  The block holding the instance's last tile waits
+// until every word of the instance carries this launch's epoch (which also proves every
+// contributing block has flushed), adds the sums in block (or tile) order and writes the
+// result.  Sums are thus identical from run to run for a given launch configuration.
 //
 // Compaction: each wave packs the kept values of its part of a sub-tile into its own LDS
-// region; at the end of the tile the block publishes the tile's count, one wave walks back
-// over the published counts of earlier tiles (a decoupled look-back, 256 descriptors per
-// step) to the tile's exclusive prefix, and every wave copies its regions out, contiguous
-// and coalesced.  Waits only ever target lower-numbered tiles, held by blocks that are all
-// resident (the grid is sized by occupancy), so they end; every wait is bounded and reports
-// a device error instead of hanging.
+// region, and the block publishes the tile's count when the tile is done.  A single-program
+// pass resolves the tile's exclusive prefix one tile later, while the block's next tile is
+// staged in a second buffer: tiles are handed out in rounds of G (tile r*G + b to block b),
+// the prefix of tile r*G + b is the base of round r plus the counts of tiles r*G .. r*G+b-1
+// (all published a round ago, read in one step of 512 descriptors), and block G-1 publishes
+// the next round's base when it resolves the last tile of a round.  No wait then sits on the
+// path of the block's own loads; the copy-out of the staged regions is contiguous and
+// coalesced.  A batched launch (many programs) resolves each tile at once by a decoupled
+// look-back over the inclusive / aggregate counts of earlier tiles of its instance.  Waits
+// only ever target lower-numbered tiles held by blocks that are all resident (the grid is
+// sized by occupancy), so they end; every wait is bounded and reports a device error
+// instead of hanging.
 //
 // Dynamic LDS layout (bytes): [lds_slots][blockDim] u64 | [lds_sums][blockDim] f64 |
-// [lds_cemit][substeps * waves][256U] u32.
+// NBUF x [lds_cemit][substeps * waves][256U] u32 (NBUF = 2 for a single program, else 1).
 
-constexpr int LB_WINDOW = 4;  // look-back descriptors per lane per step
+constexpr int LB_WINDOW = 8;  // look-back descriptors per lane per step
 
 // SPEC = 1 marks a kernel compiled at run time for one program (its own symbol in traces).
 template <int U, bool INLINE, int LB, int SPEC = 0>
@@ -296,7 +315,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     for (int k = 0; k < A.lds_slots; ++k) lacc[k * B + tid] = 0;
     for (int k = 0; k < A.lds_sums; ++k) lsum[k * B + tid] = 0.0;
     if (tid < 64) L.exptab[tid] = SG_EXPF_TAB[tid];
-    __syncthreads();
+    lds_barrier();
 
     // Combine the block's exact accumulators of instance `cur`, publish its buffered tiles;
     // the block holding the instance's last tile finalizes.
@@ -324,8 +343,14 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         }
         __builtin_amdgcn_s_waitcnt(0);  // accumulator updates complete before the tiles are published
         __syncthreads();
+        // a single program publishes one running sum per block (its tiles in order), indexed
+        // by block; a batched launch one word set per buffered tile
         bool has_last = false;
-        for (int q = 0; q < ntl; ++q) has_last |= L.tile[q] == tile0 + ntiles - 1;
+        if (INLINE) {
+            has_last = (int64_t)blockIdx.x == (ntiles - 1) % (int64_t)gridDim.x;
+        } else {
+            for (int q = 0; q < ntl; ++q) has_last |= L.tile[q] == tile0 + ntiles - 1;
+        }
         const int words = 1 + 2 * nsum;
         for (int idx = tid; idx < ntl * words; idx += B) {
             const int q = idx / words, w = idx % words;
@@ -334,7 +359,8 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 const uint64_t bits = __builtin_bit_cast(uint64_t, L.tsum[q][(w - 1) >> 1]);
                 payload = ((w - 1) & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits;  // low half first
             }
-            __hip_atomic_store(&A.tags[L.tile[q] * TAG_WORDS + w], tag_word(epoch, payload), __ATOMIC_RELAXED,
+            const int64_t where = INLINE ? (int64_t)blockIdx.x : L.tile[q];
+            __hip_atomic_store(&A.tags[where * TAG_WORDS + w], tag_word(epoch, payload), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -342,11 +368,15 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         if (!has_last) return;
         // ---- finalize the instance ----
         InstResult* res = A.results + cur;
+        // word sets to wait for: one per block (single program; every block holds a tile) or
+        // one per tile of the instance
+        const int64_t nq = INLINE ? (int64_t)gridDim.x : ntiles;
+        const int64_t q0 = INLINE ? 0 : tile0;
         for (uint32_t spins = 0;; ++spins) {
             int ok = 1;
-            for (int64_t q = tid; q < ntiles; q += B)
+            for (int64_t q = tid; q < nq; q += B)
                 for (int w = 0; w < words; ++w) {
-                    const uint64_t x = __hip_atomic_load(&A.tags[(tile0 + q) * TAG_WORDS + w], __ATOMIC_RELAXED,
+                    const uint64_t x = __hip_atomic_load(&A.tags[(q0 + q) * TAG_WORDS + w], __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                     ok &= (uint32_t)(x >> 32) == epoch;
                 }
@@ -359,8 +389,8 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         }
         for (int k = 0; k < nsum; ++k) {
             double s = 0.0;
-            for (int64_t q = tid; q < ntiles; q += B) {
-                const uint64_t* tw = A.tags + (tile0 + q) * TAG_WORDS + 1 + 2 * k;
+            for (int64_t q = tid; q < nq; q += B) {
+                const uint64_t* tw = A.tags + (q0 + q) * TAG_WORDS + 1 + 2 * k;
                 const uint64_t lo = __hip_atomic_load(tw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t hi = __hip_atomic_load(tw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 s += __builtin_bit_cast(double, ((hi & 0xFFFFFFFFull) << 32) | (lo & 0xFFFFFFFFull));
@@ -390,14 +420,71 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         __syncthreads();
     };
 
-    // ---- compaction of the current tile ----
+    // ---- compaction state ----
+    const int64_t stage_buf = (int64_t)A.lds_cemit * C * nwaves * RW;
+    int sb = 0;          // staging buffer of the tile being computed
+    int64_t pend = -1;   // single program: the tile staged in buffer sb ^ 1, awaiting its prefix
+    int pnreg = 0;
     const uint64_t lb_epoch = (uint64_t)(epoch & 0x3FFFFFFFu) << 32;
     constexpr uint64_t LB_AGG = 1ull << 62, LB_INC = 2ull << 62;
+    constexpr uint64_t LB_EPOCH_MASK = 0x3FFFFFFFull << 32;
 
-    // wave 0: exclusive prefix of tile `pend` by a decoupled look-back; publishes its
-    // inclusive count and leaves the prefix (or -1 when none can be used) in L.excl
-    auto resolve = [&](int64_t pend) {
-        const uint64_t total = L.ptotal;
+    // wave 0, single program: exclusive prefix of the staged tile `p` (buffer `buf`) from its
+    // round's base and the counts of the round's earlier tiles; publishes the next round's
+    // base when `p` closes a round; leaves the prefix (or -1 when none can be used) in L.excl
+    auto resolve_round = [&](int64_t p, int buf) {
+        const uint64_t total = L.ptotal[buf];
+        const int64_t G = (int64_t)gridDim.x, local = p - tile0, r = local / G, b = local % G;
+        uint64_t* rbase = A.lookback + A.total_tiles;  // base of round r at rbase[r]
+        int64_t excl = 0;
+        uint32_t spins = 0;
+        if (r > 0) {
+            for (;;) {
+                const uint64_t d = ld_relaxed(&rbase[r]);
+                if ((d & LB_EPOCH_MASK) == lb_epoch && (d >> 62) != 0) {
+                    excl = (int64_t)(uint32_t)d;
+                    break;
+                }
+                if (++spins > (1u << 22)) { excl = -1; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        for (int64_t j0 = 0; j0 < b && excl >= 0; j0 += 64 * LB_WINDOW) {
+            for (;;) {
+                uint64_t d[LB_WINDOW];
+#pragma unroll
+                for (int m = 0; m < LB_WINDOW; ++m) {
+                    const int64_t k = j0 + 64 * m + lane;
+                    d[m] = k < b ? ld_relaxed(&A.lookback[tile0 + r * G + k]) : (LB_AGG | lb_epoch);
+                }
+                bool valid = true;
+                int64_t part = 0;
+#pragma unroll
+                for (int m = 0; m < LB_WINDOW; ++m) {
+                    valid &= (d[m] & LB_EPOCH_MASK) == lb_epoch && (d[m] >> 62) != 0;
+                    part += (j0 + 64 * m + lane < b) ? (int64_t)(uint32_t)d[m] : 0;
+                }
+                if (__ballot(!valid) == 0) {
+                    excl += wave_sum_i64(part);
+                    break;
+                }
+                if (++spins > (1u << 22)) { excl = -1; break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (excl < 0 && lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
+        // the last tile of a full round opens the next one (its base is published even after
+        // a timed-out wait, so that later rounds do not wait on it; the launch reports the error)
+        if (b == G - 1 && (r + 1) * G < ntiles && lane == 0)
+            st_relaxed(&rbase[r + 1], LB_AGG | lb_epoch | (uint64_t)(uint32_t)((excl >= 0 ? (uint64_t)excl : 0) + total));
+        if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
+        if (lane == 0) L.excl = excl;
+    };
+
+    // wave 0, batched launch: exclusive prefix of tile `pend` (buffer 0) by a decoupled
+    // look-back; publishes its inclusive count and leaves the prefix (or -1) in L.excl
+    auto resolve_chain = [&](int64_t pend) {
+        const uint64_t total = L.ptotal[0];
         int64_t excl = 0;
         if (pend != tile0) {
             // descriptors at distance p + 1 = 1 + 64m + lane, nearest first
@@ -448,20 +535,22 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
         if (lane == 0) L.excl = excl;
     };
-    // every wave: copy the tile's regions out at L.excl; deferred contract indices
-    auto copy_out = [&](int nreg) {
+    // every wave: copy the regions of the tile staged in `buf` out at L.excl; deferred
+    // contract indices
+    auto copy_out = [&](int buf, int nreg) {
         const int64_t excl = L.excl;
+        const uint32_t* sbase = stage + buf * stage_buf;
         uint64_t dbest0 = 0, dbest1 = 0;
         for (int rg = wave; rg < nreg && excl >= 0; rg += nwaves) {
-            const uint32_t cnt = L.rcnt[rg];
-            const int64_t ob = excl + L.roff[rg];
+            const uint32_t cnt = L.rcnt[buf][rg];
+            const int64_t ob = excl + L.roff[buf][rg];
             for (int ci = 0; ci < nce; ++ci) {
                 uint32_t* q = (uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1));
-                const uint32_t* st = stage + ((int64_t)ci * C * nwaves + rg) * RW;
+                const uint32_t* st = sbase + ((int64_t)ci * C * nwaves + rg) * RW;
                 for (uint32_t i = lane; i < cnt; i += 64) q[ob + i] = st[i];
             }
             for (int ci = 0; ci < nd; ++ci) {
-                const uint32_t f = L.dfirst[ci][rg];
+                const uint32_t f = L.dfirst[buf][ci][rg];
                 if (f != 0xFFFFFFFFu) {
                     const uint64_t e = ~(uint64_t)(ob + f);
                     if (ci == 0) dbest0 = e > dbest0 ? e : dbest0;
@@ -594,7 +683,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 };
                 const int region = c * nwaves + wave;
                 for (int ci = 0; ci < nce; ++ci) {
-                    uint32_t* st = stage + ((int64_t)ci * C * nwaves + region) * RW;
+                    uint32_t* st = stage + sb * stage_buf + ((int64_t)ci * C * nwaves + region) * RW;
                     SG_ON_REG(ci == 0 ? ce_reg0 : ce_reg1, _Pragma("unroll") for (int v = 0; v < V; ++v)
                         if ((keep >> v) & 1u) st[rank_of(v)] = r[v];)
                 }
@@ -603,9 +692,9 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                     uint32_t f = hit ? rank_of(__builtin_ctz(hit)) : 0xFFFFFFFFu;
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) f = min(f, (uint32_t)__shfl_xor(f, o));
-                    if (lane == 0) L.dfirst[ci][region] = f;
+                    if (lane == 0) L.dfirst[sb][ci][region] = f;
                 }
-                if (lane == 0) L.rcnt[region] = agg;
+                if (lane == 0) L.rcnt[sb][region] = agg;
             }
 
             // ---------------- start the loads of the block's next sub-tile ----------------
@@ -634,28 +723,39 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             }
         }
 
-        // ---------------- tile end: publish the tile's count, resolve its prefix, copy out -----
+        // ---------------- tile end: publish the tile's count; resolve and copy out a prefix ----
         if (SG_GEN_HAS_SCAN && scan_space != 0) {
-            __syncthreads();
+            lds_barrier();
             const int nreg = cend * nwaves;  // regions written in this tile (at most 64)
             if (wave == 0) {
-                const uint32_t cnt = lane < nreg ? L.rcnt[lane] : 0u;
+                const uint32_t cnt = lane < nreg ? L.rcnt[sb][lane] : 0u;
                 uint32_t incl = cnt;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
                     const uint32_t y = __shfl_up(incl, o);
                     if (lane >= o) incl += y;
                 }
-                L.roff[lane] = incl - cnt;
+                L.roff[sb][lane] = incl - cnt;
                 const uint64_t total = (uint64_t)__shfl(incl, 63);
                 if (lane == 0) {
-                    L.ptotal = total;
-                    st_relaxed(&A.lookback[t], (t == tile0 ? LB_INC : LB_AGG) | lb_epoch | total);
+                    L.ptotal[sb] = total;
+                    st_relaxed(&A.lookback[t], (!INLINE && t == tile0 ? LB_INC : LB_AGG) | lb_epoch | total);
                 }
-                resolve(t);
+                if (INLINE) {
+                    if (pend >= 0) resolve_round(pend, sb ^ 1);
+                } else {
+                    resolve_chain(t);
+                }
             }
-            __syncthreads();
-            copy_out(nreg);
+            lds_barrier();
+            if (INLINE) {
+                if (pend >= 0) copy_out(sb ^ 1, pnreg);
+                pend = t;
+                pnreg = nreg;
+                sb ^= 1;
+            } else {
+                copy_out(0, nreg);
+            }
         }
         // tile end: its sums, added over the lanes and then the waves in a fixed order, are
         // buffered for publication
@@ -665,15 +765,23 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             s = wave_sum_f64(s);
             if (lane == 0) L.sum[wave][k] = s;
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < nsum) {
             double s = 0.0;
             for (int w = 0; w < nwaves; ++w) s += L.sum[w][tid];
-            L.tsum[ntl][tid] = s;
+            if (INLINE) L.tsum[0][tid] = ntl == 0 ? s : L.tsum[0][tid] + s;  // the block's running sum
+            else L.tsum[ntl][tid] = s;
         }
-        if (tid == 0) L.tile[ntl] = t;
-        __syncthreads();
-        ++ntl;
+        if (tid == 0) L.tile[INLINE ? 0 : ntl] = t;
+        lds_barrier();
+        ntl = INLINE ? 1 : ntl + 1;
+    }
+    // single program: the block's last staged tile
+    if (INLINE && SG_GEN_HAS_SCAN && pend >= 0) {
+        if (wave == 0) resolve_round(pend, sb ^ 1);
+        lds_barrier();
+        copy_out(sb ^ 1, pnreg);
+        lds_barrier();
     }
     if (cur >= 0) flush();
 }

@@ -144,9 +144,9 @@ sg_status features(sg_program_s* P, const sg_plan* plan, const std::vector<sg_no
     int occ = 0;
     for (auto& ip : tmp.insts) {
         const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
-        const int C = stream_substeps(plan->substeps, plan->block, plan->unroll, ns, ip.nsum, ce, ip.scan_space != 0);
-        const int o = sg_stream_occupancy(plan->unroll, true, plan->block,
-                                          stream_lds_bytes(ns, ip.nsum, ce, C, plan->block, plan->unroll));
+        const int C = stream_substeps(plan->substeps, plan->block, plan->unroll, ns, ip.nsum, ce, ip.scan_space != 0, 2);
+        const size_t lds = stream_lds_bytes(ns, ip.nsum, ce, C, plan->block, plan->unroll, 2);
+        const int o = std::min(sg_stream_occupancy(plan->unroll, true, plan->block, lds), lds_blocks_per_cu(lds));
         occ = occ == 0 ? o : std::min(occ, o);
     }
     f[23] = (float)occ;  // resident blocks per CU of the tightest pass

@@ -188,3 +188,17 @@ def test_pass_runs_on_the_selected_kernel(sg, ctx):
         assert spec_launches >= 1 and interp_launches == 0
     else:
         assert interp_launches >= 1 and spec_launches == 0
+
+
+@pytest.mark.parametrize("plan", [(256, 1, 1, -1), (256, 2, 1, -1), (512, 2, 1, -1), (128, 4, 1, -1), (64, 1, 1, -1)])
+def test_compaction_many_rounds(sg, ctx, plan):
+    """Compaction with one sub-tile per tile: many tiles per block, so every tile's prefix comes
+    from a round base and the counts of its round; the grid must be resident as a whole."""
+    n = 3_000_017
+    spec = W.cfg2_spec(n, with_keys=False)
+    inp = W.cfg2_inputs(n, with_keys=False)
+    built = sg.build_spec(ctx, spec, to_dev(inp))
+    built.program.set_plan(plan)
+    say("compaction plan", plan)
+    status, verdicts = built.program.execute()
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
