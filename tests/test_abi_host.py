@@ -98,3 +98,22 @@ def test_device_exp_slow_path_cases(lib):
     assert len(idx) == slow
     ref = oracle.exp_rn32(t[idx])
     assert np.array_equal(got[idx].view(np.uint32), ref.view(np.uint32))
+
+
+def test_device_exp_fast_path_sweep(tmp_path):
+    """The fast path of the device exp agrees with its double-double path wherever it does not
+    flag a hard case (every 61st binary32 argument of the finite, nonzero range; the same
+    program with stride 1 is the exhaustive sweep)."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "exp_sweep")
+    subprocess.run([gxx, "-O2", "-std=c++20", "-ffp-contract=off", "-pthread", os.path.join(here, "exp_sweep.cpp"),
+                    "-o", exe], check=True)
+    r = subprocess.run([exe, "61", "8"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    total, hard, bad = (int(v) for v in r.stdout.split()[1::2])
+    assert bad == 0 and total > 36_000_000 and hard < total // 500
