@@ -56,13 +56,15 @@ float key_to_float(int32_t k) {
 }  // namespace
 
 // Blocks per CU a pass may count on being resident together.  A pass that compacts waits on
-// other blocks' tiles, so all of its grid must be resident: the runtime's occupancy figure
+// other blocks' tiles, so all of its grid must be resident.  The runtime's occupancy figure
 // has been seen to admit one block per CU too many (when LDS is filled exactly, and when the
-// scalar registers bound a small kernel at 7 waves per SIMD), so such passes keep one block
-// per CU in reserve.
-int coresident_blocks(int occupancy, bool waits_on_others) {
-    if (!waits_on_others) return std::max(occupancy, 1);
-    return std::max(occupancy >= 3 ? occupancy - 1 : occupancy, 1);
+// scalar registers bound a small kernel at 7 waves per SIMD).  When LDS alone binds, the
+// conservative LDS count (a reserve and a bound on the static part) is used as it is;
+// otherwise a waiting pass keeps one block per CU in reserve.
+int coresident_blocks(int occupancy, int lds_blocks, bool waits_on_others) {
+    const int occ = std::max(std::min(occupancy, lds_blocks), 1);
+    if (!waits_on_others || lds_blocks < occupancy) return occ;
+    return std::max(occ >= 3 ? occ - 1 : occ, 1);
 }
 
 int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes, bool waits) {
@@ -72,10 +74,10 @@ int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, 
     if (it != ctx->occupancy.end()) {
         nb = it->second;
     } else {
-        nb = std::min(sg_stream_occupancy(unroll, inl, block, lds_bytes), lds_blocks_per_cu(lds_bytes));
+        nb = sg_stream_occupancy(unroll, inl, block, lds_bytes);
         ctx->occupancy[key] = nb;
     }
-    const int64_t cap = (int64_t)coresident_blocks(nb, waits) * ctx->num_cu;
+    const int64_t cap = (int64_t)coresident_blocks(nb, lds_blocks_per_cu(lds_bytes), waits) * ctx->num_cu;
     return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cap));
 }
 
@@ -302,7 +304,7 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         g.ntiles = (nsub + g.C - 1) / g.C;
         const bool waits = ip.scan_space != 0;
         if (jks[i]) {
-            const int occ = coresident_blocks(std::min(jit_occupancy(jks[i], block, g.lds), lds_blocks_per_cu(g.lds)), waits);
+            const int occ = coresident_blocks(jit_occupancy(jks[i], block, g.lds), lds_blocks_per_cu(g.lds), waits);
             g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, (int64_t)occ * ctx->num_cu));
         } else {
             g.grid = stream_grid(ctx, g.ntiles, true, g.U, block, g.lds, waits);

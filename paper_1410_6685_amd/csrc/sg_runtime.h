@@ -176,7 +176,7 @@ void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_valu
 sg_status alloc_output(sg_ctx_s* ctx, sg_node_s* n);
 sg_status assemble_verdicts(sg_program_s* P, const sg::InstResult* results, std::vector<sg_verdict>& V);
 int stream_grid(sg_ctx_s* ctx, int64_t ntiles, bool inl, int unroll, int block, size_t lds_bytes, bool waits);
-int coresident_blocks(int occupancy, bool waits_on_others);
+int coresident_blocks(int occupancy, int lds_blocks, bool waits_on_others);
 // Launch shape of a pass: sub-tiles per tile (clamped when values are staged for
 // compaction) and the dynamic LDS bytes of its per-lane accumulators and staging regions.
 int inst_cemit(const InstPlan& ip);
