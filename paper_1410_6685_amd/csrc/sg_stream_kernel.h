@@ -565,7 +565,13 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     };
 
     uint32_t R[NREG][V];
-    bool pf = false;  // R[0..nin) already hold the inputs of the next sub-tile
+    // Inputs of the block's next sub-tile.  The interpreter loads them into R once the
+    // program is done with R; a specialized kernel (few registers in use) loads them into N
+    // before the program runs, so they are in flight for the whole sub-tile.
+    constexpr bool EARLY = SPEC == 1;
+    constexpr int NB = EARLY && SG_GEN_NIN > 1 ? (SG_GEN_NIN < MAX_IN ? SG_GEN_NIN : MAX_IN) : 1;
+    uint32_t N[NB][V];
+    bool pf = false;  // the inputs of the sub-tile about to run are already loaded (R, or N if EARLY)
 
     for (int64_t t = blockIdx.x; t < A.total_tiles; t += gridDim.x) {
         const int64_t t_next = t + (int64_t)gridDim.x;
@@ -631,7 +637,10 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
 #pragma unroll
             for (int k = 0; k < NREG; ++k) {
                 if (k < nin && k < SG_GEN_NIN) {
-                    if (!pf) {
+                    if (EARLY && pf && k < NB) {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) R[k][v] = N[k < NB ? k : 0][v];
+                    } else if (!pf) {
                         const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
                         if (vec) {
 #pragma unroll
@@ -654,6 +663,32 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             }
             nce = 0;
             nd = 0;
+
+            // the block's next sub-tile: this tile's next one, else the first of the next tile
+            int64_t nb = -1;
+            if (c + 1 < cend) nb = sub_base + sub_elems;
+            else if (INLINE && t_next < A.total_tiles) nb = (t_next - tile0) * C * sub_elems;
+            const bool nvec = nb >= 0 && nb + sub_elems <= n && (flags & 1);
+            if (EARLY) {
+                pf = nvec;
+                if (nvec) {
+                    const int64_t ne0 = nb + (int64_t)wave * RW + lane * 4;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        if (k < nin) {
+                            const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
+#pragma unroll
+                            for (int u = 0; u < U; ++u) {
+                                const uint4 w = *(const uint4*)(q + ne0 + u * 256);
+                                N[k][4 * u + 0] = w.x;
+                                N[k][4 * u + 1] = w.y;
+                                N[k][4 * u + 2] = w.z;
+                                N[k][4 * u + 3] = w.w;
+                            }
+                        }
+                    }
+                }
+            }
 
 #include SG_PROGRAM_INC
 
@@ -697,12 +732,9 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 if (lane == 0) L.rcnt[sb][region] = agg;
             }
 
-            // ---------------- start the loads of the block's next sub-tile ----------------
-            {
-                int64_t nb = -1;
-                if (c + 1 < cend) nb = sub_base + sub_elems;
-                else if (INLINE && t_next < A.total_tiles) nb = (t_next - tile0) * C * sub_elems;
-                pf = nb >= 0 && nb + sub_elems <= n && (flags & 1);
+            // ---------------- start the loads of the block's next sub-tile (interpreter) ----------
+            if (!EARLY) {
+                pf = nvec;
                 if (pf) {
                     const int64_t ne0 = nb + (int64_t)wave * RW + lane * 4;
 #pragma unroll
