@@ -129,15 +129,10 @@ SG_HD float exp_rn_slow(float t) {
 // 16 units of the half-way pattern 2^28.  Results below the binary32 normal range take the
 // slow path (their rounding position differs).
 SG_HD float exp_rn_fast(float t, const double* tab, bool& hard) {
-    hard = false;
-    if (t != t) return t;
-    if (t >= u2f(SG_EXP_OVF_BITS)) return __builtin_inff();
-    if (t <= u2f(SG_EXP_UNF_BITS)) return 0.0f;
-    if (t < -87.0f) {  // exp(t) < 2^-125.5: near or below the binary32 normal range
-        hard = true;
-        return 0.0f;
-    }
-    const double td = (double)t;
+    // Branch-free: the core runs on t clamped into [-87, 89] (where k fits and 2^(k>>6) is a
+    // normal double), then the special cases select their own result.
+    const float tc = __builtin_fminf(__builtin_fmaxf(t, -87.0f), 89.0f);
+    const double td = (double)tc;
     const double sh = fma(td, SG_EXPF_INV_L, 0x1.8p52);
     const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, sh);
     const double kd = sh - 0x1.8p52;
@@ -150,8 +145,14 @@ SG_HD float exp_rn_fast(float t, const double* tab, bool& hard) {
     const double T = tab[k & 63];
     const double y = fma(T, p, T) * pow2d(k >> 6);
     const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, y) & 0x1FFFFFFFu;
-    hard = low - (0x10000000u - 16u) <= 32u;
-    return (float)y;
+    // exp(t) < 2^-125.5 (t < -87) is near or below the binary32 normal range: slow path
+    const bool special = t != t || t >= u2f(SG_EXP_OVF_BITS) || t <= u2f(SG_EXP_UNF_BITS);
+    hard = !special && (t < -87.0f || low - (0x10000000u - 16u) <= 32u);
+    float f = (float)y;
+    f = t <= u2f(SG_EXP_UNF_BITS) || t < -87.0f ? 0.0f : f;
+    f = t >= u2f(SG_EXP_OVF_BITS) ? __builtin_inff() : f;
+    f = t != t ? t : f;
+    return f;
 }
 
 // Correctly rounded binary32 exp.  *slow (if given) is incremented when the double-double
