@@ -320,6 +320,15 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     // Combine the block's exact accumulators of instance `cur`, publish its buffered tiles;
     // the block holding the instance's last tile finalizes.
     auto flush = [&]() {
+        // single program: the block's sums, over lanes then waves in a fixed order
+        if (INLINE) {
+            for (int k = 0; k < nsum; ++k) {
+                double s = lsum[k * B + tid];
+                lsum[k * B + tid] = 0.0;
+                s = wave_sum_f64(s);
+                if (lane == 0) L.sum[wave][k] = s;
+            }
+        }
         for (int k = 0; k < ns; ++k) {
             const uint8_t kind = d8_lane<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, slot_kind) + k);
             uint64_t v = lacc[k * B + tid];
@@ -328,6 +337,11 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             if (lane == 0) L.slot[wave][k] = v;
         }
         __syncthreads();
+        if (INLINE && tid < nsum) {
+            double s = 0.0;
+            for (int w = 0; w < nwaves; ++w) s += L.sum[w][tid];
+            L.tsum[0][tid] = s;
+        }
         if (tid < ns) {
             const uint8_t kind = d8_lane<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, slot_kind) + tid);
             uint64_t v = 0;
@@ -429,10 +443,11 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     constexpr uint64_t LB_AGG = 1ull << 62, LB_INC = 2ull << 62;
     constexpr uint64_t LB_EPOCH_MASK = 0x3FFFFFFFull << 32;
 
-    // wave 0, single program: exclusive prefix of the staged tile `p` (buffer `buf`) from its
-    // round's base and the counts of the round's earlier tiles; publishes the next round's
-    // base when `p` closes a round; leaves the prefix (or -1 when none can be used) in L.excl
-    auto resolve_round = [&](int64_t p, int buf) {
+    // every wave, single program: exclusive prefix of the staged tile `p` (buffer `buf`) from
+    // its round's base and the counts of the round's earlier tiles (every wave reads the same
+    // published values, so all get the same prefix, or -1 when none can be used); wave 0
+    // publishes the next round's base when `p` closes a round
+    auto resolve_round = [&](int64_t p, int buf) -> int64_t {
         const uint64_t total = L.ptotal[buf];
         const int64_t G = (int64_t)gridDim.x, local = p - tile0, r = local / G, b = local % G;
         uint64_t* rbase = A.lookback + A.total_tiles;  // base of round r at rbase[r]
@@ -475,10 +490,10 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         if (excl < 0 && lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
         // the last tile of a full round opens the next one (its base is published even after
         // a timed-out wait, so that later rounds do not wait on it; the launch reports the error)
-        if (b == G - 1 && (r + 1) * G < ntiles && lane == 0)
+        if (b == G - 1 && (r + 1) * G < ntiles && wave == 0 && lane == 0)
             st_relaxed(&rbase[r + 1], LB_AGG | lb_epoch | (uint64_t)(uint32_t)((excl >= 0 ? (uint64_t)excl : 0) + total));
         if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
-        if (lane == 0) L.excl = excl;
+        return excl;
     };
 
     // wave 0, batched launch: exclusive prefix of tile `pend` (buffer 0) by a decoupled
@@ -535,10 +550,10 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         if (excl >= 0 && (uint64_t)excl + total > (uint64_t)n) excl = -1;  // never past the capacity
         if (lane == 0) L.excl = excl;
     };
-    // every wave: copy the regions of the tile staged in `buf` out at L.excl; deferred
-    // contract indices
-    auto copy_out = [&](int buf, int nreg) {
-        const int64_t excl = L.excl;
+    // every wave: copy the regions this wave staged for the tile in `buf` out at `excl`;
+    // deferred contract indices.  A wave reads only the regions it wrote, so it may stage
+    // the next tile into the buffer as soon as its own copy is done.
+    auto copy_out = [&](int buf, int nreg, int64_t excl) {
         const uint32_t* sbase = stage + buf * stage_buf;
         uint64_t dbest0 = 0, dbest1 = 0;
         for (int rg = wave; rg < nreg && excl >= 0; rg += nwaves) {
@@ -773,46 +788,45 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                     L.ptotal[sb] = total;
                     st_relaxed(&A.lookback[t], (!INLINE && t == tile0 ? LB_INC : LB_AGG) | lb_epoch | total);
                 }
-                if (INLINE) {
-                    if (pend >= 0) resolve_round(pend, sb ^ 1);
-                } else {
-                    resolve_chain(t);
-                }
+                if (!INLINE) resolve_chain(t);
             }
-            lds_barrier();
             if (INLINE) {
-                if (pend >= 0) copy_out(sb ^ 1, pnreg);
+                // the previous tile: its offsets and total were made visible by the barrier above
+                if (pend >= 0) copy_out(sb ^ 1, pnreg, resolve_round(pend, sb ^ 1));
                 pend = t;
                 pnreg = nreg;
                 sb ^= 1;
             } else {
-                copy_out(0, nreg);
+                lds_barrier();
+                copy_out(0, nreg, L.excl);
             }
         }
-        // tile end: its sums, added over the lanes and then the waves in a fixed order, are
-        // buffered for publication
-        for (int k = 0; k < nsum; ++k) {
-            double s = lsum[k * B + tid];
-            lsum[k * B + tid] = 0.0;
-            s = wave_sum_f64(s);
-            if (lane == 0) L.sum[wave][k] = s;
+        // batched launch, tile end: its sums, added over the lanes and then the waves in a
+        // fixed order, are buffered for publication (a single program keeps per-lane sums
+        // until it flushes)
+        if (!INLINE) {
+            for (int k = 0; k < nsum; ++k) {
+                double s = lsum[k * B + tid];
+                lsum[k * B + tid] = 0.0;
+                s = wave_sum_f64(s);
+                if (lane == 0) L.sum[wave][k] = s;
+            }
+            lds_barrier();
+            if (tid < nsum) {
+                double s = 0.0;
+                for (int w = 0; w < nwaves; ++w) s += L.sum[w][tid];
+                L.tsum[ntl][tid] = s;
+            }
+            if (tid == 0) L.tile[ntl] = t;
+            lds_barrier();
         }
-        lds_barrier();
-        if (tid < nsum) {
-            double s = 0.0;
-            for (int w = 0; w < nwaves; ++w) s += L.sum[w][tid];
-            if (INLINE) L.tsum[0][tid] = ntl == 0 ? s : L.tsum[0][tid] + s;  // the block's running sum
-            else L.tsum[ntl][tid] = s;
-        }
-        if (tid == 0) L.tile[INLINE ? 0 : ntl] = t;
-        lds_barrier();
         ntl = INLINE ? 1 : ntl + 1;
     }
-    // single program: the block's last staged tile
+    // single program: the block's last staged tile (its offsets were written by wave 0 after
+    // the last tile's first barrier)
     if (INLINE && SG_GEN_HAS_SCAN && pend >= 0) {
-        if (wave == 0) resolve_round(pend, sb ^ 1);
         lds_barrier();
-        copy_out(sb ^ 1, pnreg);
+        copy_out(sb ^ 1, pnreg, resolve_round(pend, sb ^ 1));
         lds_barrier();
     }
     if (cur >= 0) flush();
