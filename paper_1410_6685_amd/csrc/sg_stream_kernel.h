@@ -183,6 +183,16 @@ __device__ __forceinline__ T* uptr(const void* p) {
     return (T*)(uintptr_t)uload64(p);
 }
 
+// Input and output vectors are global memory, but their addresses come from the instance
+// descriptor as integers.  Accessed through address-space-1 pointers they compile to global
+// (not flat) instructions, whose completion is counted apart from LDS and scalar memory, so
+// LDS traffic in a pass program never waits for the loads in flight.
+typedef unsigned int sg_u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) sg_u32x4 gu4;
+__device__ __forceinline__ const gu32* gin(uint64_t a) { return (const gu32*)(uintptr_t)a; }
+__device__ __forceinline__ gu32* gout(uint64_t a) { return (gu32*)(uintptr_t)a; }
+
 // Descriptor reads.  A single-instance launch keeps its descriptor and program in the kernel
 // argument segment: they are read through the segment pointer (address space 4, scalar
 // loads), never through the address of the by-value argument, which would make the
@@ -560,7 +570,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             const uint32_t cnt = L.rcnt[buf][rg];
             const int64_t ob = excl + L.roff[buf][rg];
             for (int ci = 0; ci < nce; ++ci) {
-                uint32_t* q = (uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1));
+                gu32* q = gout(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1)));
                 const uint32_t* st = sbase + ((int64_t)ci * C * nwaves + rg) * RW;
                 for (uint32_t i = lane; i < cnt; i += 64) q[ob + i] = st[i];
             }
@@ -586,7 +596,11 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     constexpr bool EARLY = SPEC == 1;
     constexpr int NB = EARLY && SG_GEN_NIN > 1 ? (SG_GEN_NIN < MAX_IN ? SG_GEN_NIN : MAX_IN) : 1;
     uint32_t N[NB][V];
+    // first element after each wave's part of a sub-tile (the sortedness check's neighbour
+    // of the wave's last element), loaded with the part itself
+    uint32_t NX[NB], nbr[NB];
     bool pf = false;  // the inputs of the sub-tile about to run are already loaded (R, or N if EARLY)
+    const gu32* const safe = (const gu32*)(uintptr_t)A.tags;  // target of loads with no sub-tile to fetch
 
     for (int64_t t = blockIdx.x; t < A.total_tiles; t += gridDim.x) {
         const int64_t t_next = t + (int64_t)gridDim.x;
@@ -649,18 +663,25 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             S[0] = inb;
 #pragma unroll
             for (int s = 1; s < MAX_SPACES; ++s) S[s] = 0;
+            if (EARLY) {
+                // this sub-tile's inputs (a specialized kernel's instance has exactly
+                // SG_GEN_NIN of them): prefetched into N by the previous sub-tile, else loaded
+                // now; all of them have arrived before the next prefetch is issued
+                if (pf) {
 #pragma unroll
-            for (int k = 0; k < NREG; ++k) {
-                if (k < nin && k < SG_GEN_NIN) {
-                    if (EARLY && pf && k < NB) {
+                    for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) {
+                        nbr[k] = NX[k];
 #pragma unroll
-                        for (int v = 0; v < V; ++v) R[k][v] = N[k < NB ? k : 0][v];
-                    } else if (!pf) {
-                        const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
+                        for (int v = 0; v < V; ++v) R[k][v] = N[k][v];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) {
+                        const gu32* q = gin(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k));
                         if (vec) {
 #pragma unroll
                             for (int u = 0; u < U; ++u) {
-                                const uint4 w = *(const uint4*)(q + e0 + u * 256);
+                                const sg_u32x4 w = *(const gu4*)(q + e0 + u * 256);
                                 R[k][4 * u + 0] = w.x;
                                 R[k][4 * u + 1] = w.y;
                                 R[k][4 * u + 2] = w.z;
@@ -670,10 +691,45 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
 #pragma unroll
                             for (int v = 0; v < V; ++v) R[k][v] = (inb >> v) & 1u ? q[elem(v)] : 0u;
                         }
+                        const int64_t ex = sub_base + (int64_t)(wave + 1) * RW;
+                        nbr[k] = ex < n ? q[ex] : 0u;
                     }
-                } else {
+                }
+#pragma unroll
+                for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) asm volatile("" ::"v"(R[k][v]));
+                    asm volatile("" ::"v"(nbr[k]));
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = SG_GEN_NIN; k < NREG; ++k)
 #pragma unroll
                     for (int v = 0; v < V; ++v) R[k][v] = 0u;
+            } else {
+#pragma unroll
+                for (int k = 0; k < NREG; ++k) {
+                    if (k < nin && k < SG_GEN_NIN) {
+                        if (!pf) {
+                            const gu32* q = gin(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k));
+                            if (vec) {
+#pragma unroll
+                                for (int u = 0; u < U; ++u) {
+                                    const sg_u32x4 w = *(const gu4*)(q + e0 + u * 256);
+                                    R[k][4 * u + 0] = w.x;
+                                    R[k][4 * u + 1] = w.y;
+                                    R[k][4 * u + 2] = w.z;
+                                    R[k][4 * u + 3] = w.w;
+                                }
+                            } else {
+#pragma unroll
+                                for (int v = 0; v < V; ++v) R[k][v] = (inb >> v) & 1u ? q[elem(v)] : 0u;
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) R[k][v] = 0u;
+                    }
                 }
             }
             nce = 0;
@@ -685,23 +741,25 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             else if (INLINE && t_next < A.total_tiles) nb = (t_next - tile0) * C * sub_elems;
             const bool nvec = nb >= 0 && nb + sub_elems <= n && (flags & 1);
             if (EARLY) {
+                // issued without branches (a sub-tile with nothing to fetch loads from a
+                // scratch word), so that nothing waits for these loads before the next sub-tile
                 pf = nvec;
-                if (nvec) {
-                    const int64_t ne0 = nb + (int64_t)wave * RW + lane * 4;
+                const int64_t ne0 = nvec ? nb + (int64_t)wave * RW + lane * 4 : 0;
+                const int64_t nex = nb + (int64_t)(wave + 1) * RW;
+                const int ustep = nvec ? 256 : 0;
 #pragma unroll
-                    for (int k = 0; k < NB; ++k) {
-                        if (k < nin) {
-                            const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
+                for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) {
+                    const gu32* q = gin(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k));
+                    const gu32* qn = nvec ? q + ne0 : safe;
 #pragma unroll
-                            for (int u = 0; u < U; ++u) {
-                                const uint4 w = *(const uint4*)(q + ne0 + u * 256);
-                                N[k][4 * u + 0] = w.x;
-                                N[k][4 * u + 1] = w.y;
-                                N[k][4 * u + 2] = w.z;
-                                N[k][4 * u + 3] = w.w;
-                            }
-                        }
+                    for (int u = 0; u < U; ++u) {
+                        const sg_u32x4 w = *(const gu4*)(qn + u * ustep);
+                        N[k][4 * u + 0] = w.x;
+                        N[k][4 * u + 1] = w.y;
+                        N[k][4 * u + 2] = w.z;
+                        N[k][4 * u + 3] = w.w;
                     }
+                    NX[k] = *(nvec && nex < n ? q + nex : safe);
                 }
             }
 
@@ -755,10 +813,10 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
 #pragma unroll
                     for (int k = 0; k < MAX_IN && k < NREG; ++k) {
                         if (k < nin && k < SG_GEN_NIN) {
-                            const uint32_t* q = (const uint32_t*)(uintptr_t)d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k);
+                            const gu32* q = gin(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, in) + 8 * k));
 #pragma unroll
                             for (int u = 0; u < U; ++u) {
-                                const uint4 w = *(const uint4*)(q + ne0 + u * 256);
+                                const sg_u32x4 w = *(const gu4*)(q + ne0 + u * 256);
                                 R[k][4 * u + 0] = w.x;
                                 R[k][4 * u + 1] = w.y;
                                 R[k][4 * u + 2] = w.z;
