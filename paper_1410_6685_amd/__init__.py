@@ -316,6 +316,7 @@ class Program:
         self.h = c_void_p()
         _check(load().sg_program_create(ctx.h, byref(self.h)), ctx.h)
         self._keep = []
+        self._vbuf = {}  # verdict buffers by capacity, reused between executions
 
     def __del__(self):
         if self.h and _lib is not None:
@@ -393,11 +394,14 @@ class Program:
 
     def execute(self, cap: int = 64):
         """Run the program.  Returns (status name, [Verdict...]); raises on API errors."""
-        buf = (Verdict * cap)()
+        buf = self._vbuf.get(cap)
+        if buf is None:
+            buf = self._vbuf[cap] = (Verdict * cap)()
         nv = c_int32()
         st = load().sg_program_execute(self.h, buf, cap, byref(nv))
         _check(st, self.ctx.h, ok=(0, 16, 17))
-        return STATUS[st], [buf[i] for i in range(min(nv.value, cap))]
+        # copies: the buffer is reused by the next execution
+        return STATUS[st], [Verdict.from_buffer_copy(buf[i]) for i in range(min(nv.value, cap))]
 
 
 class Mlp:

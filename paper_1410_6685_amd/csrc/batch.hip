@@ -19,7 +19,7 @@ using namespace sg;
 using namespace sgrt;
 
 hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, size_t lds_bytes,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t sg_launch_epoch_bump(uint32_t* e, hipStream_t s);
 
 struct sg_batch_s {

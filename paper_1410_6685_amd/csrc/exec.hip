@@ -20,7 +20,7 @@
 using namespace sg;
 
 hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, size_t lds_bytes,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t sg_launch_gemm_f32(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t K, hipStream_t s);
 hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
                                    int64_t N, int64_t K, int64_t nvec, double tol, double* work, InstResult* res,
@@ -296,8 +296,14 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         if (g.lds > kMaxDynamicLds)
             return fail(ctx, SG_E_UNSUPPORTED, "pass needs more LDS than a block has (per-lane accumulators); use a smaller block");
         if (ctx->specialize) {
-            sg_status js = jit_kernel(ctx, ip, g.U, block, &jks[i]);
-            if (js != SG_OK) return js;
+            InstPlan& mip = plan.insts[i];
+            if (!mip.jit || mip.jit_unroll != g.U || mip.jit_block != block) {
+                sg_status js = jit_kernel(ctx, ip, g.U, block, &mip.jit);
+                if (js != SG_OK) { mip.jit = nullptr; return js; }
+                mip.jit_unroll = g.U;
+                mip.jit_block = block;
+            }
+            jks[i] = mip.jit;
         }
         const int64_t sub_elems = (int64_t)block * 4 * g.U;
         const int64_t nsub = std::max<int64_t>(1, (ip.n + sub_elems - 1) / sub_elems);
@@ -334,6 +340,13 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         if (!ctx->timing) return;
         (void)hipEventRecord(timed.back().b, ctx->stream);
     };
+    // a streaming launch records its own events at the kernel's start and end
+    auto t_launch = [&](const char* name) -> std::pair<hipEvent_t, hipEvent_t> {
+        if (!ctx->timing) return {nullptr, nullptr};
+        hipEvent_t a = get_event(ctx, timed.size() * 2), b = get_event(ctx, timed.size() * 2 + 1);
+        timed.push_back({name, a, b});
+        return {a, b};
+    };
 
     plan.prod_result.assign(P->contracts.size(), -1);
     int next_prod = (int)plan.insts.size();
@@ -358,15 +371,14 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
             a.epoch_val = next_epoch(ctx);
             fill_inst(ip, a.inst0, 0, g.ntiles, 0);
             std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
-            t_begin(jk ? "stream_spec" : "stream");
-            if (jk) SG_HIP(ctx, jit_launch(jk, a, g.grid, block, g.lds, ctx->stream));
-            else SG_HIP(ctx, sg_launch_stream(a, g.U, true, g.grid, block, g.lds, ctx->stream));
+            const auto ev = t_launch(jk ? "stream_spec" : "stream");
+            if (jk) SG_HIP(ctx, jit_launch(jk, a, g.grid, block, g.lds, ctx->stream, ev.first, ev.second));
+            else SG_HIP(ctx, sg_launch_stream(a, g.U, true, g.grid, block, g.lds, ctx->stream, ev.first, ev.second));
             ctx->last_grid = g.grid;
             ctx->last_block = block;
             ctx->last_unroll = g.U;
             ctx->last_substeps = g.C;
             ctx->last_lds = g.lds;
-            t_end();
             for (auto* o : ip.compacted) o->count_dev = &S.results[ip.result_index].scan_count;
         } else if (step.kind == Step::GEMM) {
             sg_node_s* C = step.C;

@@ -7,11 +7,14 @@
 // registers statically and keeps only the registers the program uses.  hiprtc compiles it
 // for the device; kernels are cached per device and program (operations, constants, unroll
 // and block bound), so a program pays the compilation once per process.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -77,6 +80,16 @@ sg_status jit_kernel(sg_ctx_s* ctx, const InstPlan& ip, int unroll, int block, v
         *handle = it->second;
         return SG_OK;
     }
+    // SG_JIT_DUMP=<directory>: write each generated unit and program there (for inspection
+    // with an offline compiler)
+    if (const char* dump = std::getenv("SG_JIT_DUMP")) {
+        char path[512];
+        const size_t id = std::hash<std::string>{}(unit + prog);
+        std::snprintf(path, sizeof(path), "%s/sg_unit_%016zx.hip", dump, id);
+        if (FILE* f = std::fopen(path, "w")) { std::fputs(unit.c_str(), f); std::fclose(f); }
+        std::snprintf(path, sizeof(path), "%s/sg_program_%016zx.inc", dump, id);
+        if (FILE* f = std::fopen(path, "w")) { std::fputs(prog.c_str(), f); std::fclose(f); }
+    }
     std::vector<const char*> hdr_src, hdr_name;
     for (int i = 0; i < SG_RTC_NHEADERS; ++i) {
         hdr_src.push_back(SG_RTC_HEADER_TEXT[i]);
@@ -137,11 +150,15 @@ int jit_occupancy(void* handle, int block, size_t lds) {
     return nb;
 }
 
-hipError_t jit_launch(void* handle, const StreamArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+hipError_t jit_launch(void* handle, const StreamArgs& a, int grid, int block, size_t lds, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1) {
     auto* k = (JitKernel*)handle;
     size_t size = sizeof(StreamArgs);
     void* extra[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, (void*)&a, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size,
                      HIP_LAUNCH_PARAM_END};
+    if (e0)  // work sizes in threads
+        return hipExtModuleLaunchKernel(k->fn, (uint32_t)grid * (uint32_t)block, 1, 1, (uint32_t)block, 1, 1, lds, s,
+                                        nullptr, extra, e0, e1, 0);
     return hipModuleLaunchKernel(k->fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, (unsigned)lds, s, nullptr, extra);
 }
 

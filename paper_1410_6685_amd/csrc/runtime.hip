@@ -29,7 +29,6 @@
 using namespace sg;
 
 // ---- kernels (defined in the .hip kernel files) ---------------------------------------------
-hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, hipStream_t s);
 hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s);
 int sg_stream_occupancy(int unroll, bool inl, int block, size_t lds_bytes);
 

@@ -139,6 +139,10 @@ struct InstPlan {
     std::vector<AbsSum> abssums;
     std::vector<sg_node_s*> compacted;  // outputs whose count is the scan count
     int result_index = 0;               // slot in the results array
+    // specialized kernel of this pass (owned by the kernel cache) and the shape it was
+    // compiled for; looked up again only when the shape changes
+    void* jit = nullptr;
+    int jit_unroll = 0, jit_block = 0;
 };
 
 struct Step {
@@ -169,7 +173,9 @@ void ctx_retain(sg_ctx_s* ctx);
 // run-time specialized streaming kernels (jit.hip)
 sg_status jit_kernel(sg_ctx_s* ctx, const InstPlan& ip, int unroll, int block, void** handle);
 int jit_occupancy(void* handle, int block, size_t lds);
-hipError_t jit_launch(void* handle, const sg::StreamArgs& a, int grid, int block, size_t lds, hipStream_t s);
+// with events given, they are recorded at the kernel's own start and end
+hipError_t jit_launch(void* handle, const sg::StreamArgs& a, int grid, int block, size_t lds, hipStream_t s,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void ctx_release(sg_ctx_s* ctx);
 void fill_inst(const InstPlan& ip, sg::InstDesc& d, int64_t tile0, int64_t ntiles, int prog_off);
 void publish_inst(const InstPlan& ip, const sg::InstResult& r, bool publish_values);

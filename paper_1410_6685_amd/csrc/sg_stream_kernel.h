@@ -43,9 +43,9 @@ __device__ __forceinline__ uint32_t fu(float f) { return __builtin_bit_cast(uint
 __device__ __forceinline__ int32_t ui(uint32_t u) { return (int32_t)u; }
 
 // order-preserving int32 key of a binary32 value (-0 < +0); NaN handled by the caller
-__device__ __forceinline__ int32_t fkey(uint32_t b) {
-    int32_t s = (int32_t)b;
-    return s >= 0 ? s : (s ^ 0x7FFFFFFF);
+// all ones when bit v of m is set, else zero
+__device__ __forceinline__ uint32_t lane_mask_bit(uint32_t m, int v) {
+    return (uint32_t)((int32_t)(m << (31 - v)) >> 31);
 }
 
 __device__ __forceinline__ bool cmp_f(uint8_t op, float x, float c) {
@@ -463,26 +463,18 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         uint64_t* rbase = A.lookback + A.total_tiles;  // base of round r at rbase[r]
         int64_t excl = 0;
         uint32_t spins = 0;
-        if (r > 0) {
+        // the round's base is loaded with the first window of counts (one round trip)
+        for (int64_t j0 = 0; j0 == 0 || j0 < b; j0 += 64 * LB_WINDOW) {
+            const bool want_base = j0 == 0 && r > 0;
             for (;;) {
-                const uint64_t d = ld_relaxed(&rbase[r]);
-                if ((d & LB_EPOCH_MASK) == lb_epoch && (d >> 62) != 0) {
-                    excl = (int64_t)(uint32_t)d;
-                    break;
-                }
-                if (++spins > (1u << 22)) { excl = -1; break; }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        for (int64_t j0 = 0; j0 < b && excl >= 0; j0 += 64 * LB_WINDOW) {
-            for (;;) {
+                const uint64_t bd = want_base ? ld_relaxed(&rbase[r]) : (LB_AGG | lb_epoch);
                 uint64_t d[LB_WINDOW];
 #pragma unroll
                 for (int m = 0; m < LB_WINDOW; ++m) {
                     const int64_t k = j0 + 64 * m + lane;
                     d[m] = k < b ? ld_relaxed(&A.lookback[tile0 + r * G + k]) : (LB_AGG | lb_epoch);
                 }
-                bool valid = true;
+                bool valid = (bd & LB_EPOCH_MASK) == lb_epoch && (bd >> 62) != 0;
                 int64_t part = 0;
 #pragma unroll
                 for (int m = 0; m < LB_WINDOW; ++m) {
@@ -490,12 +482,13 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                     part += (j0 + 64 * m + lane < b) ? (int64_t)(uint32_t)d[m] : 0;
                 }
                 if (__ballot(!valid) == 0) {
-                    excl += wave_sum_i64(part);
+                    excl += (int64_t)(uint32_t)bd + wave_sum_i64(part);  // a base that was not loaded adds 0
                     break;
                 }
                 if (++spins > (1u << 22)) { excl = -1; break; }
                 __builtin_amdgcn_s_sleep(1);
             }
+            if (excl < 0) break;
         }
         if (excl < 0 && lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
         // the last tile of a full round opens the next one (its base is published even after
@@ -792,8 +785,14 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 const int region = c * nwaves + wave;
                 for (int ci = 0; ci < nce; ++ci) {
                     uint32_t* st = stage + sb * stage_buf + ((int64_t)ci * C * nwaves + region) * RW;
-                    SG_ON_REG(ci == 0 ? ce_reg0 : ce_reg1, _Pragma("unroll") for (int v = 0; v < V; ++v)
-                        if ((keep >> v) & 1u) st[rank_of(v)] = r[v];)
+                    // kept values fill the region from the front in element order, the others
+                    // from the back (a region has one slot per element), so every lane writes
+                    // without a branch and no two writes meet; only the front is copied out
+                    SG_ON_REG(ci == 0 ? ce_reg0 : ce_reg1, _Pragma("unroll") for (int v = 0; v < V; ++v) {
+                        const uint32_t rk = rank_of(v);
+                        const uint32_t back = (uint32_t)(RW - 1 - ((v >> 2) * 256 + (v & 3)) - lane * 4) + rk;
+                        st[(keep >> v) & 1u ? rk : back] = r[v];
+                    })
                 }
                 for (int ci = 0; ci < nd; ++ci) {
                     const uint32_t hit = ci == 0 ? D0 : D1;

@@ -1,16 +1,24 @@
 // Precompiled streaming kernels (the program interpreter) and their launchers.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "sg_stream_kernel.h"
 
 // ---- launchers (host) ------------------------------------------------------------------------
 
+// With events given, they are recorded at the kernel's own start and end.
 extern "C++" hipError_t sg_launch_stream(const sg::StreamArgs& a, int unroll, bool inl, int grid, int block,
-                                         size_t lds_bytes, hipStream_t s) {
+                                         size_t lds_bytes, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     using namespace sg;
-#define SG_LAUNCH(UU, LBB)                                                                                \
-    if (inl) hipLaunchKernelGGL((stream_kernel<UU, true, LBB>), dim3(grid), dim3(block), lds_bytes, s, a); \
-    else hipLaunchKernelGGL((stream_kernel<UU, false, LBB>), dim3(grid), dim3(block), lds_bytes, s, a);
+    void* args[] = {(void*)&a};
+    auto go = [&](const void* f) -> hipError_t {
+        if (e0) return hipExtLaunchKernel(f, dim3(grid), dim3(block), args, lds_bytes, s, e0, e1, 0);
+        return hipLaunchKernel(f, dim3(grid), dim3(block), args, lds_bytes, s);
+    };
+    hipError_t err = hipSuccess;
+#define SG_LAUNCH(UU, LBB)                                                       \
+    if (inl) err = go(reinterpret_cast<const void*>(&stream_kernel<UU, true, LBB>)); \
+    else err = go(reinterpret_cast<const void*>(&stream_kernel<UU, false, LBB>));
 #define SG_LAUNCH_U(LBB)               \
     switch (unroll) {                  \
         case 1: SG_LAUNCH(1, LBB); break; \
@@ -20,7 +28,7 @@ extern "C++" hipError_t sg_launch_stream(const sg::StreamArgs& a, int unroll, bo
     if (block <= 256) { SG_LAUNCH_U(256) } else { SG_LAUNCH_U(1024) }
 #undef SG_LAUNCH_U
 #undef SG_LAUNCH
-    return hipGetLastError();
+    return err != hipSuccess ? err : hipGetLastError();
 }
 
 extern "C++" hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s) {
