@@ -287,10 +287,12 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     for (size_t i = 0; i < plan.insts.size(); ++i) {
         const InstPlan& ip = plan.insts[i];
         Geo& g = geo[i];
-        const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
+        // a specialized kernel keeps its accumulators in registers: no LDS rows for them
+        const int ns = ctx->specialize ? 0 : (int)ip.slot_kind.size(), nu = ctx->specialize ? 0 : ip.nsum;
+        const int ce = inst_cemit(ip);
         for (g.U = unroll;; g.U /= 2) {
-            g.C = stream_substeps(C0, block, g.U, ns, ip.nsum, ce, ip.scan_space != 0, 2);
-            g.lds = stream_lds_bytes(ns, ip.nsum, ce, g.C, block, g.U, 2);
+            g.C = stream_substeps(C0, block, g.U, ns, nu, ce, ip.scan_space != 0, 2);
+            g.lds = stream_lds_bytes(ns, nu, ce, g.C, block, g.U, 2);
             if (g.lds <= kMaxDynamicLds || g.U == 1) break;
         }
         if (g.lds > kMaxDynamicLds)
@@ -365,8 +367,8 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
             a.ninst = 1;
             a.substeps = g.C;
             a.spread = MAX_SPREAD;
-            a.lds_slots = (int)ip.slot_kind.size();
-            a.lds_sums = ip.nsum;
+            a.lds_slots = jk ? 0 : (int)ip.slot_kind.size();
+            a.lds_sums = jk ? 0 : ip.nsum;
             a.lds_cemit = inst_cemit(ip);
             a.epoch_val = next_epoch(ctx);
             fill_inst(ip, a.inst0, 0, g.ntiles, 0);

@@ -61,9 +61,10 @@ std::string unit_source(const InstPlan& ip, int unroll, int lb) {
     char buf[512];
     std::snprintf(buf, sizeof(buf),
                   "#define SG_PROGRAM_INC \"sg_program_gen.inc\"\n#define SG_GEN_HAS_SCAN %d\n#define SG_GEN_NIN %d\n"
+                  "#define SG_GEN_NSLOTS %d\n#define SG_GEN_NSUMS %d\n"
                   "#include \"sg_stream_kernel.h\"\n"
                   "// instantiated through the name expression sg::stream_kernel<%d, true, %d, 1>\n",
-                  ip.scan_space != 0 ? 1 : 0, (int)ip.sources.size(), unroll, lb);
+                  ip.scan_space != 0 ? 1 : 0, (int)ip.sources.size(), (int)ip.slot_kind.size(), ip.nsum, unroll, lb);
     return buf;
 }
 

@@ -30,6 +30,12 @@
 #ifndef SG_GEN_HAS_SCAN
 #define SG_GEN_HAS_SCAN 1  // the program may compact (has a scan space)
 #endif
+#ifndef SG_GEN_NSLOTS
+#define SG_GEN_NSLOTS 1  // a specialized program's exact accumulators (kept in registers)
+#endif
+#ifndef SG_GEN_NSUMS
+#define SG_GEN_NSUMS 1   // and its float64 sums
+#endif
 #ifndef SG_GEN_NIN
 #define SG_GEN_NIN MAX_IN  // at most this many loaded sources
 #endif
@@ -303,13 +309,68 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     const kptr kdesc = kargs + __builtin_offsetof(StreamArgs, inst0);
     const kptr kprog = kargs + __builtin_offsetof(StreamArgs, prog0);
 
+    // Per-lane accumulators: a specialized kernel knows its slots and sums when it is compiled
+    // and keeps them in registers (no LDS traffic in the sub-tile loop); the interpreter keeps
+    // them in LDS, where a launch gives them lds_slots and lds_sums rows.
+    constexpr bool RACC = SPEC == 1;
+    constexpr int RNS = RACC && SG_GEN_NSLOTS > 0 ? SG_GEN_NSLOTS : 1;
+    constexpr int RNU = RACC && SG_GEN_NSUMS > 0 ? SG_GEN_NSUMS : 1;
+    uint64_t racc[RNS];
+    double rsum[RNU];
+#pragma unroll
+    for (int i = 0; i < RNS; ++i) racc[i] = 0;
+#pragma unroll
+    for (int i = 0; i < RNU; ++i) rsum[i] = 0.0;
     uint64_t* lacc = dyn;                                        // [slot][B]
     double* lsum = (double*)(dyn + (int64_t)A.lds_slots * B);    // [sum][B]
     uint32_t* stage = (uint32_t*)(dyn + (int64_t)(A.lds_slots + A.lds_sums) * B);
-    auto acc_add = [&](int k, uint64_t v) { lacc[k * B + tid] += v; };
+    auto acc_add = [&](int k, uint64_t v) {
+        if (RACC) {
+#pragma unroll
+            for (int i = 0; i < RNS; ++i) if (i == k) racc[i] += v;
+        } else {
+            lacc[k * B + tid] += v;
+        }
+    };
     auto acc_max = [&](int k, uint64_t v) {
-        const uint64_t o = lacc[k * B + tid];
-        lacc[k * B + tid] = v > o ? v : o;
+        if (RACC) {
+#pragma unroll
+            for (int i = 0; i < RNS; ++i) if (i == k) racc[i] = v > racc[i] ? v : racc[i];
+        } else {
+            const uint64_t o = lacc[k * B + tid];
+            lacc[k * B + tid] = v > o ? v : o;
+        }
+    };
+    auto sum_add = [&](int k, double v) {
+        if (RACC) {
+#pragma unroll
+            for (int i = 0; i < RNU; ++i) if (i == k) rsum[i] += v;
+        } else {
+            lsum[k * B + tid] += v;
+        }
+    };
+    // read an accumulator and reset it
+    auto acc_take = [&](int k) -> uint64_t {
+        uint64_t v = 0;
+        if (RACC) {
+#pragma unroll
+            for (int i = 0; i < RNS; ++i) if (i == k) { v = racc[i]; racc[i] = 0; }
+        } else {
+            v = lacc[k * B + tid];
+            lacc[k * B + tid] = 0;
+        }
+        return v;
+    };
+    auto sum_take = [&](int k) -> double {
+        double v = 0.0;
+        if (RACC) {
+#pragma unroll
+            for (int i = 0; i < RNU; ++i) if (i == k) { v = rsum[i]; rsum[i] = 0.0; }
+        } else {
+            v = lsum[k * B + tid];
+            lsum[k * B + tid] = 0.0;
+        }
+        return v;
     };
 
     // block-uniform state of the current instance
@@ -333,16 +394,14 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         // single program: the block's sums, over lanes then waves in a fixed order
         if (INLINE) {
             for (int k = 0; k < nsum; ++k) {
-                double s = lsum[k * B + tid];
-                lsum[k * B + tid] = 0.0;
+                double s = sum_take(k);
                 s = wave_sum_f64(s);
                 if (lane == 0) L.sum[wave][k] = s;
             }
         }
         for (int k = 0; k < ns; ++k) {
             const uint8_t kind = d8_lane<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, slot_kind) + k);
-            uint64_t v = lacc[k * B + tid];
-            lacc[k * B + tid] = 0;
+            uint64_t v = acc_take(k);
             v = kind == SLOT_ADD ? (uint64_t)wave_sum_i64((int64_t)v) : wave_max_u64(v);
             if (lane == 0) L.slot[wave][k] = v;
         }
@@ -565,7 +624,8 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             for (int ci = 0; ci < nce; ++ci) {
                 gu32* q = gout(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1)));
                 const uint32_t* st = sbase + ((int64_t)ci * C * nwaves + rg) * RW;
-                for (uint32_t i = lane; i < cnt; i += 64) q[ob + i] = st[i];
+                gu32* dst = q + ob;  // one base per region, 32-bit offsets per store
+                for (uint32_t i = lane; i < cnt; i += 64) dst[i] = st[i];
             }
             for (int ci = 0; ci < nd; ++ci) {
                 const uint32_t f = L.dfirst[buf][ci][rg];
@@ -863,8 +923,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         // until it flushes)
         if (!INLINE) {
             for (int k = 0; k < nsum; ++k) {
-                double s = lsum[k * B + tid];
-                lsum[k * B + tid] = 0.0;
+                double s = sum_take(k);
                 s = wave_sum_f64(s);
                 if (lane == 0) L.sum[wave][k] = s;
             }

@@ -143,9 +143,11 @@ sg_status features(sg_program_s* P, const sg_plan* plan, const std::vector<sg_no
     f[22] = (float)bytes;
     int occ = 0;
     for (auto& ip : tmp.insts) {
-        const int ns = (int)ip.slot_kind.size(), ce = inst_cemit(ip);
-        const int C = stream_substeps(plan->substeps, plan->block, plan->unroll, ns, ip.nsum, ce, ip.scan_space != 0, 2);
-        const size_t lds = stream_lds_bytes(ns, ip.nsum, ce, C, plan->block, plan->unroll, 2);
+        // the same LDS rows as the execution: none for the accumulators of a specialized kernel
+        const bool spec = P->ctx->specialize;
+        const int ns = spec ? 0 : (int)ip.slot_kind.size(), nu = spec ? 0 : ip.nsum, ce = inst_cemit(ip);
+        const int C = stream_substeps(plan->substeps, plan->block, plan->unroll, ns, nu, ce, ip.scan_space != 0, 2);
+        const size_t lds = stream_lds_bytes(ns, nu, ce, C, plan->block, plan->unroll, 2);
         const int o = std::min(sg_stream_occupancy(plan->unroll, true, plan->block, lds), lds_blocks_per_cu(lds));
         occ = occ == 0 ? o : std::min(occ, o);
     }
