@@ -25,6 +25,9 @@ HBM_PEAK_GBS = 8000.0
 N_DEFAULT = 1 << 26
 
 
+# launch plans (block, unroll, sub-tiles per tile, split) the autotuner times for the main pass
+TUNE_PLANS = [(256, 2, 8, -1), (256, 4, 8, -1), (256, 4, 2, -1), (256, 2, 4, -1), (512, 2, 4, -1), (512, 4, 2, -1),
+              (256, 1, 8, -1)]
 KERNEL_SOURCES = ("sg_stream_kernel.h", "sg_stream_ops.inc", "sg_kernels.h", "sg_exp.h", "sg_exp_table.h", "jit.hip")
 
 
@@ -299,6 +302,7 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="run the context's default launch plan (no autotuning)")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 256 MiB device copy (profiling aid)")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the matrix-product workload")
     ap.add_argument("--cfg4-instances", type=int, default=10_000, help="0 skips the batched workload")
@@ -335,6 +339,12 @@ def main():
         ctx.set_launch(args.block, args.unroll)
     built = sg.build_spec(ctx, spec, dev)
     prog = built.program
+    tuned = None
+    if not (args.block or args.unroll or args.no_tune):
+        # the framework's autotuner picks the launch plan of the hot loop once, before timing
+        print("[bench] autotuning the launch plan", file=sys.stderr, flush=True)
+        best, cand_ms = prog.autotune(TUNE_PLANS, reps=3)
+        tuned = {"plan": list(TUNE_PLANS[best]), "candidates_ms": [[list(p), round(t, 4)] for p, t in zip(TUNE_PLANS, cand_ms)]}
 
     def run_steps(k, p):
         for _ in range(k):
@@ -400,6 +410,8 @@ def main():
     extras["stream_launches_per_step"] = launches_per_step
     extras["stream_kernel_ms_per_step"] = round(k_ms / args.steps, 5)
     extras["launch_shape"] = shape
+    if tuned is not None:
+        extras["autotuned_plan"] = tuned
     del built, prog, dev
     if not args.no_extras and not args.no_cfg3:
         log("cfg3: matrix product with product ensure")
