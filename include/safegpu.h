@@ -183,6 +183,17 @@ sg_status sg_program_split(sg_program p, sg_node n);
 /* Run the program (trigger "update").  Writes up to `cap` verdicts.  Returns SG_OK,
  * SG_PRE_VIOLATED (outputs unpublished) or SG_POST_VIOLATED, or an error code. */
 sg_status sg_program_execute(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts);
+/* Asynchronous form of sg_program_execute, for loops that run a program repeatedly: launch
+ * enqueues one execution on the context's stream and returns once it is enqueued; wait blocks
+ * until the oldest pending execution has finished and returns exactly what sg_program_execute
+ * would have returned for it (status, verdicts, published values).  Up to 4 executions of a
+ * program may be pending (SG_E_STATE beyond that, or from wait with none pending).  While any
+ * is pending the program is not changed: adding roots or clauses, split, set_plan, features,
+ * time_plans, execute and a launch after a change of the context's mode return SG_E_STATE.
+ * Outputs of a later launch overwrite those of an earlier one as the stream reaches it.
+ * Releasing a program waits for its pending executions. */
+sg_status sg_program_launch(sg_program p);
+sg_status sg_program_wait(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts);
 sg_status sg_program_release(sg_program p);
 
 /* Execute roots without contracts (shorthand for a temporary program). */

@@ -91,6 +91,7 @@ def _sig(lib):
         "sg_program_close": [H, c_int, H, c_double, c_double, P(c_int32)],
         "sg_program_product": [H, c_int, H, H, H, H, P(c_int32)], "sg_program_split": [H, H],
         "sg_program_execute": [H, P(Verdict), c_int32, P(c_int32)], "sg_program_release": [H],
+        "sg_program_launch": [H], "sg_program_wait": [H, P(Verdict), c_int32, P(c_int32)],
         "sg_execute": [H, P(H), c_int32],
         "sg_scalar_get": [H, P(c_double), P(c_int64)], "sg_scalar_shadow": [H, P(c_double)],
         "sg_count": [H, P(c_int64)], "sg_to_host": [H, H, c_int64, P(c_int64)], "sg_device_ptr": [H, P(H), P(c_int64)],
@@ -391,6 +392,20 @@ class Program:
         best = c_int32()
         _check(load().sg_autotune(self.h, arr, len(plans), reps, byref(best), ms), self.ctx.h)
         return best.value, list(ms)
+
+    def launch(self):
+        """Enqueue one execution without waiting (collect it with wait(), oldest first)."""
+        _check(load().sg_program_launch(self.h), self.ctx.h)
+
+    def wait(self, cap: int = 64):
+        """Wait for the oldest launched execution; returns what execute() would have."""
+        buf = self._vbuf.get(cap)
+        if buf is None:
+            buf = self._vbuf[cap] = (Verdict * cap)()
+        nv = c_int32()
+        st = load().sg_program_wait(self.h, buf, cap, byref(nv))
+        _check(st, self.ctx.h, ok=(0, 16, 17))
+        return STATUS[st], [Verdict.from_buffer_copy(buf[i]) for i in range(min(nv.value, cap))]
 
     def execute(self, cap: int = 64):
         """Run the program.  Returns (status name, [Verdict...]); raises on API errors."""

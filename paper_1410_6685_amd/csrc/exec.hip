@@ -31,18 +31,13 @@ namespace sgrt {
 
 namespace {
 
-struct Timed {
-    const char* name;
-    hipEvent_t a, b;
-};
-
-hipEvent_t get_event(sg_ctx_s* ctx, size_t i) {
-    while (ctx->events.size() <= i) {
+hipEvent_t get_event(std::vector<hipEvent_t>& pool, size_t i) {
+    while (pool.size() <= i) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        ctx->events.push_back(e);
+        pool.push_back(e);
     }
-    return ctx->events[i];
+    return pool[i];
 }
 
 
@@ -267,8 +262,11 @@ sg_status assemble_verdicts(sg_program_s* P, const InstResult* results, std::vec
     return status;
 }
 
-sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+// Enqueue one execution: every pass, then the copy of its results into `es.host` (pinned);
+// `es.done` (when set) is recorded after the copy.  The results are read by finish_program.
+sg_status launch_program(sg_program_s* P, ExecSlot& es) {
     sg_ctx_s* ctx = P->ctx;
+    es.timed.clear();
     if (!P->plan.valid || P->plan.generation != ctx->generation) {
         sg_status st = build_plan(P, &P->plan);
         if (st != SG_OK) { P->plan.valid = false; return st; }
@@ -331,10 +329,10 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         if ((st = alloc_output(ctx, m)) != SG_OK) return st;
     Scratch& S = ctx->scratch;
 
-    std::vector<Timed> timed;
+    std::vector<Timed>& timed = es.timed;
     auto t_begin = [&](const char* name) {
         if (!ctx->timing) return;
-        hipEvent_t a = get_event(ctx, timed.size() * 2), b = get_event(ctx, timed.size() * 2 + 1);
+        hipEvent_t a = get_event(*es.events, timed.size() * 2), b = get_event(*es.events, timed.size() * 2 + 1);
         timed.push_back({name, a, b});
         (void)hipEventRecord(a, ctx->stream);
     };
@@ -345,7 +343,7 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
     // a streaming launch records its own events at the kernel's start and end
     auto t_launch = [&](const char* name) -> std::pair<hipEvent_t, hipEvent_t> {
         if (!ctx->timing) return {nullptr, nullptr};
-        hipEvent_t a = get_event(ctx, timed.size() * 2), b = get_event(ctx, timed.size() * 2 + 1);
+        hipEvent_t a = get_event(*es.events, timed.size() * 2), b = get_event(*es.events, timed.size() * 2 + 1);
         timed.push_back({name, a, b});
         return {a, b};
     };
@@ -411,10 +409,35 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
             if (e != hipSuccess) return hip_fail(ctx, e, "product check");
         }
     }
-    SG_HIP(ctx, hipMemcpyAsync(ctx->host_results, S.results, (size_t)nres * sizeof(InstResult),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (auto& t : timed) {
+    if (!es.owned) {  // the context's results, sized with the scratch
+        es.host = ctx->host_results;
+        es.host_cap = S.insts;
+    }
+    if (es.host_cap < nres) {
+        if (es.owned && es.host) (void)hipHostFree(es.host);
+        es.host = nullptr;
+        es.host_cap = 0;
+        if (!es.owned) return fail(ctx, SG_E_STATE, "result buffer too small");
+        SG_HIP(ctx, hipHostMalloc((void**)&es.host, (size_t)nres * sizeof(InstResult), hipHostMallocDefault));
+        es.host_cap = nres;
+    }
+    es.nres = nres;
+    SG_HIP(ctx, hipMemcpyAsync(es.host, S.results, (size_t)nres * sizeof(InstResult), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    if (es.done) SG_HIP(ctx, hipEventRecord(es.done, ctx->stream));
+    return SG_OK;
+}
+
+// Wait for an enqueued execution, then account its timings, check the kernels' error words,
+// assemble the verdicts and publish the values.
+sg_status finish_program(sg_program_s* P, ExecSlot& es, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+    sg_ctx_s* ctx = P->ctx;
+    Plan& plan = P->plan;
+    Scratch& S = ctx->scratch;
+    const int64_t nres = es.nres;
+    if (es.done) SG_HIP(ctx, hipEventSynchronize(es.done));
+    else SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto& t : es.timed) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
             ctx->times[t.name].ms += ms;
@@ -422,7 +445,7 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
         }
     }
     for (int64_t i = 0; i < nres; ++i) {
-        if (const uint32_t err = ctx->host_results[i].err) {
+        if (const uint32_t err = es.host[i].err) {
             // reset the state the kernels keep between launches, then report
             (void)hipMemsetAsync(S.base, 0, S.bytes, ctx->stream);
             (void)hipStreamSynchronize(ctx->stream);
@@ -437,15 +460,26 @@ sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, in
 
     const int nc = (int)P->contracts.size();
     std::vector<sg_verdict> V;
-    sg_status status = assemble_verdicts(P, ctx->host_results, V);
+    sg_status status = assemble_verdicts(P, es.host, V);
     const bool publish = status != SG_PRE_VIOLATED;
-    for (auto& ip : plan.insts) publish_inst(ip, ctx->host_results[ip.result_index], publish);
+    for (auto& ip : plan.insts) publish_inst(ip, es.host[ip.result_index], publish);
     for (auto& step : plan.steps)
         if (step.kind == Step::GEMM) step.C->state = publish ? ST_COMPUTED : ST_UNPUBLISHED;
     if (nverdicts) *nverdicts = nc;
     if (verdicts)
         for (int i = 0; i < nc && i < cap; ++i) verdicts[i] = V[i];
     return status;
+}
+
+sg_status execute_program(sg_program_s* P, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+    if (!P->pending.empty()) return fail(P->ctx, SG_E_STATE, "execute: the program has pending launches; wait for them first");
+    sg_ctx_s* ctx = P->ctx;
+    // the context's pinned results (sized with the scratch) and its event pool
+    ExecSlot es;
+    es.events = &ctx->events;
+    sg_status st = launch_program(P, es);
+    if (st != SG_OK) return st;
+    return finish_program(P, es, verdicts, cap, nverdicts);
 }
 
 }  // namespace sgrt
@@ -467,8 +501,15 @@ sg_status sg_program_create(sg_ctx ctx, sg_program* out) {
     return SG_OK;
 }
 
+// a program with pending launches is not changed (their results are read against its plan)
+static sg_status check_idle(sg_program p, const char* what) {
+    if (!p->pending.empty()) return fail(p->ctx, SG_E_STATE, std::string(what) + ": the program has pending launches");
+    return SG_OK;
+}
+
 sg_status sg_program_add_root(sg_program p, sg_node n) {
     if (!p || !n) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "add_root: NULL argument");
+    if (sg_status st = check_idle(p, "add_root")) return st;
     if (n->ctx != p->ctx) return fail(p->ctx, SG_E_INVALID, "add_root: node of another context");
     retain(n);
     p->roots.push_back(n);
@@ -477,6 +518,7 @@ sg_status sg_program_add_root(sg_program p, sg_node n) {
 }
 
 static sg_status add_contract(sg_program p, sgrt::Contract c, int32_t* id) {
+    if (sg_status st = check_idle(p, "contract")) return st;
     if (c.kind != SG_REQUIRE && c.kind != SG_ENSURE) return fail(p->ctx, SG_E_INVALID, "contract kind must be require or ensure");
     c.id = p->next_contract++;
     for (auto* n : {c.node, c.a, c.b, c.r}) retain(n);
@@ -541,6 +583,7 @@ sg_status sg_program_product(sg_program p, sg_clause kind, sg_node C, sg_node A,
 
 sg_status sg_program_split(sg_program p, sg_node n) {
     if (!p || !n) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "split: NULL argument");
+    if (sg_status st = check_idle(p, "split")) return st;
     retain(n);
     p->splits.push_back(n);
     p->plan.valid = false;
@@ -553,9 +596,50 @@ sg_status sg_program_execute(sg_program p, sg_verdict* verdicts, int32_t cap, in
     return execute_program(p, verdicts, cap, nverdicts);
 }
 
+sg_status sg_program_launch(sg_program p) {
+    if (!p) return fail(nullptr, SG_E_INVALID, "launch: NULL program");
+    if ((int)p->pending.size() >= sg_program_s::kMaxPending)
+        return fail(p->ctx, SG_E_STATE, "launch: too many pending launches; wait for one first");
+    // a plan that needs rebuilding would no longer match the pending launches' results
+    if (!p->pending.empty() && (!p->plan.valid || p->plan.generation != p->ctx->generation))
+        return fail(p->ctx, SG_E_STATE, "launch: the program or its context changed while launches are pending");
+    int slot = 0;
+    for (int i = 0; i < sg_program_s::kMaxPending; ++i) {
+        bool used = false;
+        for (int q : p->pending) used |= q == i;
+        if (!used) { slot = i; break; }
+    }
+    ExecSlot& es = p->slots[slot];
+    es.owned = true;
+    es.events = &es.own_events;
+    if (!es.done && hipEventCreateWithFlags(&es.done, hipEventDisableTiming) != hipSuccess) {
+        es.done = nullptr;
+        return fail(p->ctx, SG_E_DEVICE, "launch: event creation failed");
+    }
+    sg_status st = launch_program(p, es);
+    if (st != SG_OK) return st;
+    p->pending.push_back(slot);
+    return SG_OK;
+}
+
+sg_status sg_program_wait(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
+    if (!p) return fail(nullptr, SG_E_INVALID, "wait: NULL program");
+    if (cap < 0 || (cap > 0 && !verdicts)) return fail(p->ctx, SG_E_INVALID, "wait: bad verdict buffer");
+    if (p->pending.empty()) return fail(p->ctx, SG_E_STATE, "wait: no pending launch");
+    const int slot = p->pending.front();
+    p->pending.pop_front();
+    return finish_program(p, p->slots[slot], verdicts, cap, nverdicts);
+}
+
 sg_status sg_program_release(sg_program p) {
     if (!p) return SG_E_INVALID;
     if (--p->refs > 0) return SG_OK;
+    if (!p->pending.empty()) (void)hipStreamSynchronize(p->ctx->stream);  // copies into the slots end first
+    for (auto& es : p->slots) {
+        if (es.owned && es.host) (void)hipHostFree(es.host);
+        if (es.done) (void)hipEventDestroy(es.done);
+        for (hipEvent_t e : es.own_events) (void)hipEventDestroy(e);
+    }
     for (auto* r : p->roots) release(r);
     for (auto& c : p->contracts) {
         for (auto* n : {c.node, c.a, c.b, c.r}) release(n);

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <map>
 #include <tuple>
 #include <string>
@@ -162,6 +163,23 @@ struct Plan {
     bool valid = false;
 };
 
+struct Timed {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+// Where one execution's results and timing events go: the context's pinned results and event
+// pool for a synchronous execution, a slot of the program for an asynchronous launch.
+struct ExecSlot {
+    sg::InstResult* host = nullptr;      // results copied back (pinned host memory)
+    int64_t host_cap = 0, nres = 0;
+    bool owned = false;                  // host allocated for this slot (else the context's)
+    hipEvent_t done = nullptr;           // recorded after the copy (asynchronous launches)
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t>* events = nullptr;  // pool the timing events are drawn from
+    std::vector<hipEvent_t> own_events;
+};
+
 sg_status fail(sg_ctx_s* ctx, sg_status st, const std::string& msg);
 sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what);
 void* dev_alloc(sg_ctx_s* ctx, size_t bytes);
@@ -218,6 +236,10 @@ struct sg_program_s {
     sg_node_s* plan_split = nullptr;  // extra fusion split point of the plan
     sgrt::Plan plan;
     int32_t next_contract = 0;
+    // asynchronous launches: slots in use, oldest first (the program is not changed meanwhile)
+    static constexpr int kMaxPending = 4;
+    sgrt::ExecSlot slots[kMaxPending];
+    std::deque<int> pending;
 };
 
 struct sg_batch_s;

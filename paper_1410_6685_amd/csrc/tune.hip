@@ -167,6 +167,7 @@ sg_status sg_program_split_candidates(sg_program p, int32_t* n) {
 
 sg_status sg_program_set_plan(sg_program p, const sg_plan* plan) {
     if (!p) return fail(nullptr, SG_E_INVALID, "set_plan: NULL program");
+    if (!p->pending.empty()) return fail(p->ctx, SG_E_STATE, "set_plan: the program has pending launches");
     if (!plan) {
         p->block = p->unroll = p->substeps = 0;
         p->plan_split = nullptr;
@@ -182,12 +183,14 @@ sg_status sg_program_set_plan(sg_program p, const sg_plan* plan) {
 
 sg_status sg_program_features(sg_program p, const sg_plan* plan, float* f24) {
     if (!p || !f24 || !valid_plan(plan)) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "features: bad argument");
+    if (!p->pending.empty()) return fail(p->ctx, SG_E_STATE, "features: the program has pending launches");
     return features(p, plan, split_candidates(p), f24);
 }
 
 // Device time (ms, median of `reps` executions after one warm-up) of each plan.
 sg_status sg_program_time_plans(sg_program p, const sg_plan* plans, int32_t n, int32_t reps, double* ms_out) {
     if (!p || !plans || n < 1 || reps < 1 || !ms_out) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "time_plans: bad argument");
+    if (!p->pending.empty()) return fail(p->ctx, SG_E_STATE, "time_plans: the program has pending launches");
     sg_ctx_s* ctx = p->ctx;
     auto cands = split_candidates(p);
     const bool timing = ctx->timing;
