@@ -303,6 +303,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="run the context's default launch plan (no autotuning)")
+    ap.add_argument("--sync", action="store_true", help="synchronous steps (execute) instead of launch/wait pipelining")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 256 MiB device copy (profiling aid)")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the matrix-product workload")
     ap.add_argument("--cfg4-instances", type=int, default=10_000, help="0 skips the batched workload")
@@ -346,11 +347,22 @@ def main():
         best, cand_ms = prog.autotune(TUNE_PLANS, reps=3)
         tuned = {"plan": list(TUNE_PLANS[best]), "candidates_ms": [[list(p), round(t, 4)] for p, t in zip(TUNE_PLANS, cand_ms)]}
 
+    def check(st):
+        if st not in ("ok", "post_violated"):
+            raise RuntimeError(f"unexpected status {st}")
+
     def run_steps(k, p):
-        for _ in range(k):
-            st, _ = p.execute()
-            if st not in ("ok", "post_violated"):
-                raise RuntimeError(f"unexpected status {st}")
+        if args.sync or k == 0:
+            for _ in range(k):
+                check(p.execute()[0])
+            return
+        # pipelined: step i+1 is enqueued before the verdicts of step i are collected, so the
+        # host's per-step work overlaps the previous step's kernel; every step is checked
+        p.launch()
+        for i in range(k):
+            if i + 1 < k:
+                p.launch()
+            check(p.wait()[0])
 
     def timed(mode: str, steps: int, warmup: int, p=None):
         p = p or prog
@@ -410,6 +422,7 @@ def main():
     extras["stream_launches_per_step"] = launches_per_step
     extras["stream_kernel_ms_per_step"] = round(k_ms / args.steps, 5)
     extras["launch_shape"] = shape
+    extras["steps_pipelined"] = not args.sync  # launch/wait: host work overlaps the previous step
     if tuned is not None:
         extras["autotuned_plan"] = tuned
     del built, prog, dev
