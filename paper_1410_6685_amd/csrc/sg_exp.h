@@ -128,6 +128,28 @@ SG_HD float exp_rn_slow(float t) {
 // place, so RN32(y) = RN32(exp t) unless the 29 bits below binary32 precision lie within
 // 16 units of the half-way pattern 2^28.  Results below the binary32 normal range take the
 // slow path (their rounding position differs).
+// The float64 core alone, for an ordinary argument: -87 <= t < the overflow threshold.
+SG_HD float exp_rn_core(float t, const double* tab, bool& hard) {
+    const double td = (double)t;
+    const double sh = fma(td, SG_EXPF_INV_L, 0x1.8p52);
+    const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, sh);
+    const double kd = sh - 0x1.8p52;
+    double r = fma(-kd, SG_EXPF_L1, td);
+    r = fma(-kd, SG_EXPF_L2, r);
+    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    const double p = fma(q, r * r, r);  // exp(r) - 1
+    const double T = tab[k & 63];
+    const double y = fma(T, p, T) * pow2d(k >> 6);
+    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, y) & 0x1FFFFFFFu;
+    hard = low - (0x10000000u - 16u) <= 32u;
+    return (float)y;
+}
+
+// an argument the core handles (NaN fails both comparisons)
+SG_HD bool exp_ordinary(float t) { return t >= -87.0f && t < u2f(SG_EXP_OVF_BITS); }
+
 SG_HD float exp_rn_fast(float t, const double* tab, bool& hard) {
     // Branch-free: the core runs on t clamped into [-87, 89] (where k fits and 2^(k>>6) is a
     // normal double), then the special cases select their own result.

@@ -1,5 +1,6 @@
 // Sweep of the device exp's fast path on the host: wherever it does not flag a hard case,
-// its result equals the double-double path's.  Every `stride`-th binary32 argument in
+// its result equals the double-double path's; for ordinary arguments the bare core gives the
+// fast path's result and flag.  Every `stride`-th binary32 argument in
 // [underflow threshold, overflow threshold); stride 1 is the exhaustive sweep.
 #include <atomic>
 #include <cstdint>
@@ -25,6 +26,14 @@ int main(int argc, char** argv) {
                 bool hd;
                 const float f = sgx::exp_rn_fast(t, SG_EXPF_TAB, hd);
                 ++n;
+                if (sgx::exp_ordinary(t)) {
+                    bool hc;
+                    const float fc = sgx::exp_rn_core(t, SG_EXPF_TAB, hc);
+                    if (hc != hd || (!hd && sgx::f2u(fc) != sgx::f2u(f))) {
+                        if (b < 5) std::printf("core differs t=%a\n", t);
+                        ++b;
+                    }
+                }
                 if (hd) { ++h; continue; }
                 if (sgx::f2u(f) != sgx::f2u(sgx::exp_rn_slow(t))) {
                     if (b < 5) std::printf("mismatch t=%a fast=%a\n", t, f);
