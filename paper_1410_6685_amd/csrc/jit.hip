@@ -71,7 +71,7 @@ std::string unit_source(const InstPlan& ip, int unroll, int lb) {
 }  // namespace
 
 sg_status jit_kernel(sg_ctx_s* ctx, const InstPlan& ip, int unroll, int block, void** handle) {
-    const int lb = block <= 256 ? 256 : 1024;
+    const int lb = block <= 256 ? 256 : block <= 512 ? 512 : 1024;  // register budget follows the block
     const std::string prog = program_source(ip);
     const std::string unit = unit_source(ip, unroll, lb);
     const auto key = std::make_tuple(ctx->device, unit + prog);
