@@ -9,8 +9,8 @@
 //   1. BW = [B r_v | |B| |r_v|]          (K x 8)
 //   2. AW = [A BW_v | |A| BW_(4+v)]       (M x 8)
 //   3. C r_v, compared row by row with AW.
-// Each pass is a row-by-matrix product with an 8-column right-hand side staged in LDS;
-// a wave works on two rows at a time, reading 16 bytes per lane.
+// Each pass is a row-by-matrix product with an 8-column right-hand side read through the
+// caches; a wave works on two rows at a time, reading 16 bytes per lane.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -19,7 +19,6 @@
 
 namespace sg {
 
-constexpr int PCH = 1024;  // right-hand-side rows staged per LDS chunk
 constexpr int PRW = 2;     // rows per wave
 
 __device__ __forceinline__ double wsum(double v) {
@@ -31,13 +30,15 @@ __device__ __forceinline__ double wsum(double v) {
 // out[i][c] = sum_j f_c(X[i][j]) W[j][c], f_c(x) = x for c < 4 and |x| for c >= 4 (NW = 8).
 // W comes from R (nvec x cols floats; column c is r_c for c < 4, |r_(c-4)| for c >= 4) or from
 // a cols x 8 double matrix Wd.  With cmp != null (NW = 4) the rows are compared with cmp.
+// W (at most cols x 8 doubles) is read directly and stays in the caches; each lane owns the
+// columns 4 lane + 256 k, taken in increasing order, and two of its column groups are loaded
+// before either is used, so a wave keeps several loads of X and W in flight.
 template <int NW>
 __global__ __launch_bounds__(256) void rowdot_kernel(const float* __restrict__ X, int64_t rows, int64_t cols,
                                                      const float* __restrict__ R, int nvec,
                                                      const double* __restrict__ Wd, double* __restrict__ out,
                                                      const double* __restrict__ cmp, double tol,
                                                      InstResult* res, int zero_res) {
-    __shared__ double Ws[PCH][NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (zero_res && blockIdx.x == 0 && tid == 0) {
         res->slot[0] = 0;
@@ -50,59 +51,83 @@ __global__ __launch_bounds__(256) void rowdot_kernel(const float* __restrict__ X
     for (int r = 0; r < PRW; ++r)
 #pragma unroll
         for (int c = 0; c < NW; ++c) acc[r][c] = 0.0;
-    const bool vec = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    const bool vec = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0) && (R == nullptr || (uintptr_t)R % 16 == 0);
 
-    for (int64_t c0 = 0; c0 < cols; c0 += PCH) {
-        __syncthreads();
-        for (int idx = tid; idx < PCH * NW; idx += 256) {
-            const int j = idx / NW, c = idx % NW;
-            const int64_t gj = c0 + j;
-            double w = 0.0;
-            if (gj < cols) {
-                if (Wd) {
-                    w = Wd[gj * 8 + c];
-                } else {
-                    const int v = c & 3;
-                    if (v < nvec) {
-                        const float rv = R[(int64_t)v * cols + gj];
-                        w = c < 4 ? (double)rv : (double)__builtin_fabsf(rv);
+    // one group: columns j..j+3 of this lane's rows, and the matching rows of W
+    struct Group {
+        float x[PRW][4];
+        double w[4][NW];
+    };
+    auto load = [&](int64_t j, Group& g) {
+        const bool full = vec && j + 3 < cols;
+#pragma unroll
+        for (int r = 0; r < PRW; ++r) {
+            const int64_t row = row0 + r;
+            const float* xp = X + row * cols + j;
+            if (row < rows && full) {
+                const float4 v = *(const float4*)xp;
+                g.x[r][0] = v.x; g.x[r][1] = v.y; g.x[r][2] = v.z; g.x[r][3] = v.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) g.x[r][q] = (row < rows && j + q < cols) ? xp[q] : 0.f;
+            }
+        }
+        if (Wd) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < NW; ++c) g.w[q][c] = j + q < cols ? Wd[(j + q) * 8 + c] : 0.0;
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float rv[4] = {0.f, 0.f, 0.f, 0.f};
+                if (v < nvec) {
+                    const float* rp = R + (int64_t)v * cols + j;
+                    if (full) {
+                        const float4 t = *(const float4*)rp;
+                        rv[0] = t.x; rv[1] = t.y; rv[2] = t.z; rv[3] = t.w;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) rv[q] = j + q < cols ? rp[q] : 0.f;
                     }
                 }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    g.w[q][v] = (double)rv[q];
+                    if (NW == 8) g.w[q][(v + 4) % NW] = (double)__builtin_fabsf(rv[q]);
+                }
             }
-            Ws[j][c] = w;
         }
-        __syncthreads();
-        const int64_t lim = cols - c0 < PCH ? cols - c0 : PCH;
-        for (int64_t j = 4 * lane; j < lim; j += 256) {
-            float x[PRW][4];
+    };
+    auto use = [&](int64_t j, const Group& g) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (j + q >= cols) break;
 #pragma unroll
             for (int r = 0; r < PRW; ++r) {
-                const int64_t row = row0 + r;
-                const float* xp = X + row * cols + c0 + j;
-                if (row < rows && vec && j + 3 < lim) {
-                    const float4 v = *(const float4*)xp;
-                    x[r][0] = v.x; x[r][1] = v.y; x[r][2] = v.z; x[r][3] = v.w;
-                } else {
+                const double xv = (double)g.x[r][q];
+                const double ax = xv < 0 ? -xv : xv;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) x[r][q] = (row < rows && j + q < lim) ? xp[q] : 0.f;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (j + q >= lim) break;
-                double w[NW];
-#pragma unroll
-                for (int c = 0; c < NW; ++c) w[c] = Ws[j + q][c];
-#pragma unroll
-                for (int r = 0; r < PRW; ++r) {
-                    const double xv = (double)x[r][q];
-                    const double ax = xv < 0 ? -xv : xv;
-#pragma unroll
-                    for (int c = 0; c < NW; ++c) acc[r][c] += (c < 4 ? xv : ax) * w[c];
-                }
+                for (int c = 0; c < NW; ++c) acc[r][c] += (c < 4 ? xv : ax) * g.w[q][c];
             }
         }
+    };
+    int64_t j = 4 * lane;
+    for (; j + 256 < cols; j += 512) {
+        Group g0, g1;
+        load(j, g0);
+        load(j + 256, g1);
+        use(j, g0);
+        use(j + 256, g1);
     }
+    if (j < cols) {
+        Group g0;
+        load(j, g0);
+        use(j, g0);
+    }
+    // the largest ratio |e| / b of the block goes out with one atomic (nonnegative doubles
+    // order as their bit patterns); violations, rare, each with their own
+    uint64_t worst = 0;
 #pragma unroll
     for (int r = 0; r < PRW; ++r) {
         const int64_t row = row0 + r;
@@ -122,8 +147,19 @@ __global__ __launch_bounds__(256) void rowdot_kernel(const float* __restrict__ X
                 double ratio = b > 0 ? ae / b : (ae == 0 ? 0.0 : __builtin_inf());
                 if (ratio != ratio) ratio = __builtin_inf();
                 if (!ok) atomicMax((unsigned long long*)&res->slot[0], (unsigned long long)~(((uint64_t)v << 40) | (uint64_t)row));
-                atomicMax((unsigned long long*)&res->sum[0], (unsigned long long)__builtin_bit_cast(uint64_t, ratio));
+                const uint64_t rb = __builtin_bit_cast(uint64_t, ratio);
+                worst = rb > worst ? rb : worst;
             }
+        }
+    }
+    if (cmp) {
+        __shared__ uint64_t wmax[4];
+        if (lane == 0) wmax[wave] = worst;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t m = 0;
+            for (int w = 0; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+            if (m) atomicMax((unsigned long long*)&res->sum[0], (unsigned long long)m);
         }
     }
 }
