@@ -83,6 +83,39 @@ def log(msg: str) -> None:
 MFMA_FP32_PEAK_TFLOPS = 157.3
 
 
+def run_cfg1(ctx, steps: int, warmup: int, n: int = 1 << 20) -> dict:
+    """Plain vs fused: z = (2x+1) + y, s = sum z with its contracts at n = 2^20 (a working set
+    that fits the 256 MB last-level cache: the figure of merit is time, not HBM rate).  Fused:
+    one streaming pass; unfused: one pass per operation and contract."""
+    import torch
+
+    import paper_1410_6685_amd as sg
+    import workloads as W
+
+    inp = W.cfg1_inputs(n)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+    built = sg.build_spec(ctx, W.cfg1_spec(n), dev)
+    ctx.set_mode("pre_post")
+    out = {"n": n}
+    for fused in (True, False):
+        ctx.set_fusion(fused)
+        try:
+            for _ in range(warmup):
+                built.program.execute()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                status, _ = built.program.execute()
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / steps * 1e6
+        finally:
+            ctx.set_fusion(True)
+        out["fused_us" if fused else "unfused_us"] = round(us, 2)
+        out["status"] = status
+    out["fusion_speedup"] = round(out["unfused_us"] / out["fused_us"], 3)
+    return out
+
+
 def run_cfg3(ctx, steps: int, warmup: int, n: int = 4096) -> dict:
     """C = A B on FP32 MFMA with the Freivalds ensure (4 probe vectors, float64 check)."""
     import torch
@@ -429,6 +462,8 @@ def main():
     if not args.no_extras and not args.no_cfg3:
         log("cfg3: matrix product with product ensure")
         extras["cfg3_matmul"] = run_cfg3(ctx, max(3, args.steps // 2), 2)
+        log("cfg1: plain vs fused chain, n = 2^20")
+        extras["cfg1_fusion"] = run_cfg1(ctx, max(20, args.steps), 5)
         torch.cuda.empty_cache()
     if not args.no_extras and args.cfg4_instances > 0:
         ctx.set_specialize(False)
