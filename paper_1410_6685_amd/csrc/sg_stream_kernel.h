@@ -175,13 +175,16 @@ __device__ __forceinline__ void set_space(uint32_t (&S)[MAX_SPACES], int s, uint
     }
 }
 
-// block-uniform loads from a descriptor in kernarg or global memory
+// Block-uniform reads of data that no kernel writes while this one runs (descriptor and
+// program tables, tile map, a count written by an earlier launch): through the constant
+// address space they are scalar loads, served by the scalar cache without a vector round trip.
+#define SG_AS4 __attribute__((address_space(4)))
 __device__ __forceinline__ uint32_t uload32(const void* p) {
-    return __builtin_amdgcn_readfirstlane(*(const uint32_t*)p);
+    return *(const SG_AS4 uint32_t*)(const SG_AS4 char*)p;
 }
 __device__ __forceinline__ uint64_t uload64(const void* p) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(((const uint32_t*)p)[0]);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(((const uint32_t*)p)[1]);
+    const uint32_t lo = *(const SG_AS4 uint32_t*)(const SG_AS4 char*)p;
+    const uint32_t hi = *((const SG_AS4 uint32_t*)(const SG_AS4 char*)p + 1);
     return ((uint64_t)hi << 32) | lo;
 }
 template <class T>
@@ -203,22 +206,20 @@ __device__ __forceinline__ gu32* gout(uint64_t a) { return (gu32*)(uintptr_t)a; 
 // argument segment: they are read through the segment pointer (address space 4, scalar
 // loads), never through the address of the by-value argument, which would make the
 // compiler copy the whole argument block to private memory.  Batched launches read the
-// descriptor table in global memory with block-uniform loads.
+// descriptor and program tables in global memory, also with scalar loads.
 typedef const __attribute__((address_space(4))) char* kptr;
 
 template <bool INLINE>
 __device__ __forceinline__ uint32_t d32(kptr kb, const char* gb, int off) {
     if constexpr (INLINE) return *(const __attribute__((address_space(4))) uint32_t*)(kb + off);
-    else return __builtin_amdgcn_readfirstlane(*(const uint32_t*)(gb + off));
+    else return uload32(gb + off);
 }
 template <bool INLINE>
 __device__ __forceinline__ uint64_t d64(kptr kb, const char* gb, int off) {
     if constexpr (INLINE) {
         return *(const __attribute__((address_space(4))) uint64_t*)(kb + off);
     } else {
-        const uint32_t lo = __builtin_amdgcn_readfirstlane(*(const uint32_t*)(gb + off));
-        const uint32_t hi = __builtin_amdgcn_readfirstlane(*(const uint32_t*)(gb + off + 4));
-        return ((uint64_t)hi << 32) | lo;
+        return uload64(gb + off);
     }
 }
 template <bool INLINE>
