@@ -149,6 +149,11 @@ __device__ __forceinline__ uint32_t all_bits() {
         case 3: { uint32_t(&r)[V] = R[3]; __VA_ARGS__ } break; \
         default: { uint32_t(&r)[V] = R[4]; __VA_ARGS__ } break; \
     }
+// The current operation's register a (and, for MOV, its destination).  A specialized kernel
+// indexes the register file with constants; the interpreter rebinds both to a copy of the
+// operand, so that each operation's code exists once instead of once per register.
+#define SG_ON_A(...) SG_ON_REG(op.a, __VA_ARGS__)
+#define SG_ON_DST(...) SG_ON_REG(op.dst, __VA_ARGS__)
 
 __device__ __forceinline__ uint32_t get_space(const uint32_t (&S)[MAX_SPACES], int s) {
     switch (s) {
