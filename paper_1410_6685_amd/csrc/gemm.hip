@@ -3,9 +3,9 @@
 //
 // v_mfma_f32_32x32x2f32: each wave multiplies a 32x2 by a 2x32 block per instruction and
 // accumulates a 32x32 fp32 tile.  A 256-thread block computes a 128x128 tile of C (each wave
-// 64x64 = 2x2 MFMA tiles), streaming 16-wide K slices of A and B through double-buffered LDS
-// (registers hold the next slice while the current one is consumed).  Blocks are
-// reordered so that consecutive tiles of C land on the same XCD and share its L2.
+// 64x64 = 2x2 MFMA tiles), streaming K slices of A and B through LDS; registers hold the next
+// slice while the current one is consumed.  Blocks are reordered so that consecutive tiles of
+// C land on the same XCD and share its L2.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -14,14 +14,21 @@ namespace sg {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int GBM = 128, GBN = 128, GBK = 16;
+constexpr int GBM = 128, GBN = 128;
 constexpr int APAD = 1, BPAD = 4;
+// launched shape: 16-deep K slices, one LDS buffer (measured fastest of 16/32 x 1/2 buffers)
+constexpr int GBK_RUN = 16, NBUF_RUN = 1;
 
-template <bool VEC>
+// GBK: depth of a K slice (16 or 32); NBUF: LDS buffers (2: the next slice is stored while
+// the current one is consumed, one barrier per slice; 1: two barriers per slice, half the LDS)
+template <bool VEC, int GBK, int NBUF>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A, const float* __restrict__ B,
                                                        float* __restrict__ C, int M, int N, int K) {
-    __shared__ float As[2][GBM][GBK + APAD];
-    __shared__ float Bs[2][GBK][GBN + BPAD];
+    static_assert(GBK == 16 || GBK == 32, "K slice");
+    constexpr int P = GBK / 8;      // float4 loads per thread for each of A and B
+    constexpr int AQ = GBK / 4;     // float4 per row of an A slice
+    __shared__ float As[NBUF][GBM][GBK + APAD];
+    __shared__ float Bs[NBUF][GBK][GBN + BPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_n = (N + GBN - 1) / GBN;
     const int nb = gridDim.x;
@@ -38,44 +45,52 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    float ra[2][4], rb[2][4];
+    float ra[P][4], rb[P][4];
     auto load = [&](int k0) {
+        // a slice inside the matrices (every slice of a multiple-of-tile product) loads with
+        // no per-lane condition: a lane-divergent bounds branch around the 16-byte loads makes
+        // the compiler wait for all loads in flight before issuing the next, which would
+        // expose the memory latency the register prefetch is meant to hide
+        const bool inside = VEC && m0 + GBM <= M && n0 + GBN <= N && k0 + GBK <= K;
+        if (inside) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int idx = tid + 256 * p;
-            // A: 128 rows x 16 columns, 4 floats per thread-load
-            {
-                const int row = idx >> 2, kq = (idx & 3) * 4;
-                const int gm = m0 + row, gk = k0 + kq;
-                if (VEC && gm < M && gk + 3 < K) {
-                    const float4 v = *(const float4*)(A + (int64_t)gm * K + gk);
-                    ra[p][0] = v.x; ra[p][1] = v.y; ra[p][2] = v.z; ra[p][3] = v.w;
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        ra[p][q] = (gm < M && gk + q < K) ? A[(int64_t)gm * K + gk + q] : 0.f;
-                }
+            for (int p = 0; p < P; ++p) {
+                const int idx = tid + 256 * p;
+                const int row = idx / AQ, kq = (idx % AQ) * 4;
+                const float4 va = *(const float4*)(A + (int64_t)(m0 + row) * K + k0 + kq);
+                ra[p][0] = va.x; ra[p][1] = va.y; ra[p][2] = va.z; ra[p][3] = va.w;
+                const int krow = idx >> 5, nq = (idx & 31) * 4;
+                const float4 vb = *(const float4*)(B + (int64_t)(k0 + krow) * N + n0 + nq);
+                rb[p][0] = vb.x; rb[p][1] = vb.y; rb[p][2] = vb.z; rb[p][3] = vb.w;
             }
-            // B: 16 rows x 128 columns
+            return;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int idx = tid + 256 * p;
+            // A: 128 rows x GBK columns, 4 floats per thread-load
+            {
+                const int row = idx / AQ, kq = (idx % AQ) * 4;
+                const int gm = m0 + row, gk = k0 + kq;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ra[p][q] = (gm < M && gk + q < K) ? A[(int64_t)gm * K + gk + q] : 0.f;
+            }
+            // B: GBK rows x 128 columns
             {
                 const int krow = idx >> 5, nq = (idx & 31) * 4;
                 const int gk = k0 + krow, gn = n0 + nq;
-                if (VEC && gk < K && gn + 3 < N) {
-                    const float4 v = *(const float4*)(B + (int64_t)gk * N + gn);
-                    rb[p][0] = v.x; rb[p][1] = v.y; rb[p][2] = v.z; rb[p][3] = v.w;
-                } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        rb[p][q] = (gk < K && gn + q < N) ? B[(int64_t)gk * N + gn + q] : 0.f;
-                }
+                for (int q = 0; q < 4; ++q)
+                    rb[p][q] = (gk < K && gn + q < N) ? B[(int64_t)gk * N + gn + q] : 0.f;
             }
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < P; ++p) {
             const int idx = tid + 256 * p;
-            const int row = idx >> 2, kq = (idx & 3) * 4;
+            const int row = idx / AQ, kq = (idx % AQ) * 4;
 #pragma unroll
             for (int q = 0; q < 4; ++q) As[buf][row][kq + q] = ra[p][q];
             const int krow = idx >> 5, nq = (idx & 31) * 4;
@@ -90,7 +105,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     __syncthreads();
     const int li = lane & 31, lk = lane >> 5;
     for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
+        const int buf = NBUF == 2 ? (kt & 1) : 0;
         if (kt + 1 < nk) load((kt + 1) * GBK);
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 2) {
@@ -106,7 +121,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < nk) store(buf ^ 1);
+        if (NBUF == 1) __syncthreads();  // every wave is done with the buffer
+        if (kt + 1 < nk) store(NBUF == 2 ? (buf ^ 1) : 0);
         __syncthreads();
     }
     // accumulator layout: register r of lane l holds row 8*(r/4) + 4*(l/32) + (r%4), column l%32
@@ -132,8 +148,8 @@ hipError_t sg_launch_gemm_f32(const float* A, const float* B, float* C, int64_t 
     if (tiles > (1 << 30)) return hipErrorInvalidValue;
     const bool vec = (K % 4 == 0) && (N % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
     if (vec)
-        hipLaunchKernelGGL(sg::gemm_f32_kernel<true>, dim3((unsigned)tiles), dim3(256), 0, s, A, B, C, (int)M, (int)N, (int)K);
+        hipLaunchKernelGGL((sg::gemm_f32_kernel<true, sg::GBK_RUN, sg::NBUF_RUN>), dim3((unsigned)tiles), dim3(256), 0, s, A, B, C, (int)M, (int)N, (int)K);
     else
-        hipLaunchKernelGGL(sg::gemm_f32_kernel<false>, dim3((unsigned)tiles), dim3(256), 0, s, A, B, C, (int)M, (int)N, (int)K);
+        hipLaunchKernelGGL((sg::gemm_f32_kernel<false, sg::GBK_RUN, sg::NBUF_RUN>), dim3((unsigned)tiles), dim3(256), 0, s, A, B, C, (int)M, (int)N, (int)K);
     return hipGetLastError();
 }
