@@ -4,8 +4,8 @@
 // v_mfma_f32_32x32x2f32: each wave multiplies a 32x2 by a 2x32 block per instruction and
 // accumulates a 32x32 fp32 tile.  A 256-thread block computes a 128x128 tile of C (each wave
 // 64x64 = 2x2 MFMA tiles), streaming K slices of A and B through LDS; registers hold the next
-// slice while the current one is consumed.  Blocks are reordered so that consecutive tiles of
-// C land on the same XCD and share its L2.
+// slice while the current one is consumed.  Blocks are reordered so that the tiles of C one
+// XCD holds at a time form a square patch whose panels its L2 shares.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -30,11 +30,18 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     __shared__ float As[NBUF][GBM][GBK + APAD];
     __shared__ float Bs[NBUF][GBK][GBN + BPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tiles_n = (N + GBN - 1) / GBN;
+    const int tiles_m = (M + GBM - 1) / GBM, tiles_n = (N + GBN - 1) / GBN;
     const int nb = gridDim.x;
     int tile = blockIdx.x;
     if ((nb & 7) == 0) tile = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous
-    const int m0 = (tile / tiles_n) * GBM, n0 = (tile % tiles_n) * GBN;
+    // tiles in groups of 8 tile rows, column by column within a group: the blocks resident on
+    // one XCD at a time cover an 8 x 8 patch of C, so they share 8 slices of A and 8 of B
+    // (a row-major order would need 2 of A and 32 of B)
+    constexpr int G = 8;
+    const int width = G * tiles_n;
+    const int first = (tile / width) * G;
+    const int gs = tiles_m - first < G ? tiles_m - first : G;
+    const int m0 = (first + (tile % width) % gs) * GBM, n0 = ((tile % width) / gs) * GBN;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
     floatx16 acc[2][2];
