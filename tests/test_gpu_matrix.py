@@ -23,7 +23,8 @@ def gemm(sg, ctx, A, B):
     return c.to_host().reshape(A.shape[0], B.shape[1])
 
 
-@pytest.mark.parametrize("M,K,N", [(1, 1, 1), (128, 16, 128), (200, 300, 130), (257, 129, 513), (512, 1024, 256)])
+@pytest.mark.parametrize("M,K,N", [(1, 1, 1), (128, 16, 128), (200, 300, 130), (257, 129, 513), (512, 1024, 256),
+                                   (1200, 64, 300), (2176, 48, 1040), (1536, 32, 256)])
 def test_gemm_small_within_rounding_bound(sg, ctx, M, K, N):
     say("gemm", M, K, N)
     A = W.normal_f32(M * K, 31, 1.0 / np.sqrt(K)).reshape(M, K)
