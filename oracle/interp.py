@@ -77,17 +77,22 @@ def _reduce(red, vals, dtype):
             v = int(np.max(vals)) if red == "max" else int(np.min(vals))
         return {"value": v, "exact": v, "dtype": "i32"}
     if red == "avg":
+        # the mean of the collection (Section 3.3 avg): exact sum / count, correctly rounded to
+        # float64 ("exact"); a float32 collection's value is that mean rounded to float32.  An
+        # empty collection has no mean (NaN).  abs_sum / count scales the tolerance.
         if n == 0:
-            return {"value": float("nan"), "exact": float("nan"), "dtype": "f32" if dtype == "f32" else "f64"}
+            return {"value": float("nan"), "exact": float("nan"), "abs_sum": 0.0,
+                    "dtype": "f32" if dtype == "f32" else "f64"}
         if dtype == "f32":
             exact = exact_sum_f32(vals)
             if isinstance(exact, Fraction):
                 q = float(exact / n)
             else:
                 q = exact / n
-            return {"value": float(np.float32(q)), "exact": q, "dtype": "f32"}
+            with np.errstate(over="ignore"):
+                return {"value": float(np.float32(q)), "exact": q, "dtype": "f32", "abs_sum": abs_sum(vals, "f32")}
         q = float(Fraction(exact_sum(vals, "i32"), n))
-        return {"value": q, "exact": q, "dtype": "f64"}
+        return {"value": q, "exact": q, "dtype": "f64", "abs_sum": float(abs_sum(vals, "i32"))}
     raise ValueError(red)
 
 

@@ -396,3 +396,191 @@ def test_i32_chain_and_sum():
     r = oracle.evaluate(spec, {"x": x})
     vals = [((v + 7 + 2**31) % 2**32) - 2**31 for v in x.tolist()]
     assert r.values["s"]["value"] == sum(vals) and r.values["m"]["value"] == max(vals)
+
+
+# ---- every remaining element function, int32 op and predicate, and avg ------------------
+#
+# Each branch of apply_fn and eval_pred is compared with a definition computed a different
+# way: exact rationals rounded by brute force (rn32_of_fraction), bit manipulation for the
+# sign operations, C two's-complement truncation (ctypes) for int32 wrap-around, and Python
+# comparisons in explicit loops for predicates.
+
+import ctypes
+
+
+def finite_f32_sample():
+    """Normal, large, tiny and subnormal binary32 values, both signs, plus exact edge values."""
+    g = np.random.Generator(np.random.PCG64(77))
+    parts = [W.normal_f32(300, 1), W.normal_f32(100, 2, 1e18), W.normal_f32(100, 3, 1e-20),
+             (g.integers(1, 1 << 23, 100).astype(np.uint32)).view(np.float32),            # +subnormals
+             (g.integers(1, 1 << 23, 100).astype(np.uint32) | 0x80000000).view(np.float32),  # -subnormals
+             np.array([0.0, -0.0, 1.0, -1.0, 0.5, 3.0, 1.17549435e-38, -1.17549435e-38, 3.4028235e38,
+                       -3.4028235e38, 1.8446744e19, 2.0 ** -75, 2.0 ** -76], np.float32)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def bits(a):
+    return np.asarray(a, np.float32).view(np.uint32)
+
+
+def rn32_product(x, y):
+    """IEEE product: the exact product rounded; a zero result (exact or underflowed) carries
+    the exclusive-or of the operands' signs."""
+    r = rn32_of_fraction(Fraction(float(x)) * Fraction(float(y)))
+    if r == 0:
+        return np.float32(-0.0) if np.signbit(x) != np.signbit(y) else np.float32(0.0)
+    return r
+
+
+def rn32_sum(x, y):
+    """IEEE sum: the exact sum rounded; an exact zero is +0 unless both operands are -0."""
+    q = Fraction(float(x)) + Fraction(float(y))
+    if q == 0:
+        return np.float32(-0.0) if (np.signbit(x) and np.signbit(y)) else np.float32(0.0)
+    return rn32_of_fraction(q)
+
+
+def test_f32_square_add_mul_c_vs_exact_rationals():
+    x = finite_f32_sample()
+    sq, _ = apply_fn(["square"], x, "f32")
+    for xi, yi in zip(x, sq):
+        assert same_f32(yi, rn32_product(xi, xi)), (xi, yi)
+    for c in (0.1, -3.75, 1e-30, 7e25, -0.0):
+        c32 = np.float32(c)
+        ya, _ = apply_fn(["add_c", c], x, "f32")
+        ym, _ = apply_fn(["mul_c", c], x, "f32")
+        for xi, a, m in zip(x, ya, ym):
+            assert same_f32(a, rn32_sum(xi, c32)), (xi, c, a)
+            assert same_f32(m, rn32_product(xi, c32)), (xi, c, m)
+
+
+def test_f32_neg_abs_are_sign_bit_operations():
+    x = np.concatenate([finite_f32_sample(), np.array([np.inf, -np.inf, np.nan], np.float32)])
+    neg, _ = apply_fn(["neg"], x, "f32")
+    ab, _ = apply_fn(["abs"], x, "f32")
+    assert np.array_equal(bits(neg), bits(x) ^ np.uint32(0x80000000))
+    assert np.array_equal(bits(ab), bits(x) & np.uint32(0x7FFFFFFF))
+
+
+def test_f32_sqrt_brackets_the_exact_root():
+    """r = RN32(sqrt(x)) iff x lies strictly between the squares of the midpoints around r
+    (no ties are possible for sqrt of a binary32 value)."""
+    x = np.abs(finite_f32_sample())
+    r, _ = apply_fn(["sqrt"], x, "f32")
+    for xi, ri in zip(x, r):
+        X = Fraction(float(xi))
+        if X == 0:
+            assert ri == 0 and np.signbit(ri) == np.signbit(xi)
+            continue
+        lo = (Fraction(float(ri)) + Fraction(float(np.nextafter(ri, np.float32(0))))) / 2
+        hi = (Fraction(float(ri)) + Fraction(float(np.nextafter(ri, np.float32(np.inf))))) / 2
+        assert lo * lo < X < hi * hi, (xi, ri)
+    sp, _ = apply_fn(["sqrt"], np.array([-1.0, -1e-40, np.inf, np.nan, -0.0], np.float32), "f32")
+    assert np.isnan(sp[0]) and np.isnan(sp[1]) and sp[2] == np.inf and np.isnan(sp[3])
+    assert sp[4] == 0 and np.signbit(sp[4])
+    sa, _ = apply_fn(["sqrt_abs"], np.array([-4.0, -0.0, -np.inf], np.float32), "f32")
+    assert sa.tolist() == [2.0, 0.0, np.inf] and not np.signbit(sa[1])
+
+
+def test_f32_special_values_follow_ieee():
+    x = np.array([np.inf, -np.inf, np.nan], np.float32)
+    sq, _ = apply_fn(["square"], x, "f32")
+    assert sq[0] == np.inf and sq[1] == np.inf and np.isnan(sq[2])
+    m0, _ = apply_fn(["mul_c", 0.0], x, "f32")
+    assert np.all(np.isnan(m0))                     # inf * 0 is invalid
+    a, _ = apply_fn(["add_c", -1e30], x, "f32")
+    assert a[0] == np.inf and a[1] == -np.inf and np.isnan(a[2])
+    big, _ = apply_fn(["square"], np.array([1e20, -2e19], np.float32), "f32")
+    assert np.all(big == np.inf)                     # overflow rounds to infinity
+
+
+def test_i2f_rounds_exact_integers_to_nearest_even():
+    g = np.random.Generator(np.random.PCG64(78))
+    v = np.concatenate([g.integers(-2**31, 2**31, 3000).astype(np.int64),
+                        np.array([0, 1, -1, 2**24, 2**24 + 1, 2**24 + 3, -(2**24 + 1), 2**31 - 1, -2**31,
+                                  16777217, 33554435, 2**30 + 64, 2**30 + 65])]).astype(np.int32)
+    got, dt = apply_fn(["i2f"], v, "i32")
+    assert dt == "f32"
+    for vi, gi in zip(v.tolist(), got):
+        assert same_f32(gi, rn32_of_fraction(Fraction(vi))), (vi, gi)
+    # the halfway case 2^24 + 1 rounds to the even neighbour 2^24
+    assert float(apply_fn(["i2f"], np.array([2**24 + 1], np.int32), "i32")[0][0]) == 2.0 ** 24
+
+
+def c_i32(v: int) -> int:
+    return ctypes.c_int32(v).value  # C conversion to a 32-bit two's-complement integer
+
+
+def test_i32_square_neg_abs_add_mul_wrap_like_c():
+    g = np.random.Generator(np.random.PCG64(79))
+    x = np.concatenate([g.integers(-2**31, 2**31, 2000),
+                        np.array([0, 1, -1, 46340, 46341, -46341, 65536, 2**31 - 1, -2**31])]).astype(np.int32)
+    cases = {"square": lambda a: a * a, "neg": lambda a: -a, "abs": lambda a: abs(a),
+             ("add_c", 2**31 - 5): lambda a: a + (2**31 - 5), ("mul_c", -7919): lambda a: a * -7919,
+             ("affine", 65537, -3): lambda a: 65537 * a - 3}
+    for key, f in cases.items():
+        fn = [key] if isinstance(key, str) else list(key)
+        got, dt = apply_fn(fn, x, "i32")
+        assert dt == "i32"
+        assert [c_i32(f(int(a))) for a in x.tolist()] == got.tolist(), fn
+    # the edge cases a two's-complement machine produces
+    assert apply_fn(["neg"], np.array([-2**31], np.int32), "i32")[0][0] == -2**31
+    assert apply_fn(["abs"], np.array([-2**31], np.int32), "i32")[0][0] == -2**31
+
+
+def test_i32_predicate_truth_table():
+    vals = [-2**31, -1000, -5, -1, 0, 1, 5, 1000, 2**31 - 1]
+    x = np.array(vals, np.int32)
+    py = {"lt": lambda a, c: a < c, "le": lambda a, c: a <= c, "gt": lambda a, c: a > c,
+          "ge": lambda a, c: a >= c, "eq": lambda a, c: a == c, "ne": lambda a, c: a != c}
+    for op, f in py.items():
+        for c in (-5, 0, 1, 2**31 - 1, -2**31):
+            assert eval_pred(["cmp", op, c], x, "i32").tolist() == [f(a, c) for a in vals], (op, c)
+    assert eval_pred(["in_range", -5, 5], x, "i32").tolist() == [-5 <= a <= 5 for a in vals]
+    assert eval_pred(["isfinite"], x, "i32").tolist() == [True] * len(vals)
+    assert eval_pred(["true"], x, "i32").tolist() == [True] * len(vals)
+    p = ["or", ["cmp", "lt", -999], ["and", ["cmp", "ge", 0], ["not", ["cmp", "eq", 5]]]]
+    assert eval_pred(p, x, "i32").tolist() == [(a < -999) or (a >= 0 and not a == 5) for a in vals]
+    with pytest.raises(ValueError):
+        eval_pred(["cmp", "gt", 0.5], x, "i32")  # an int predicate constant must be integral
+
+
+def avg_spec(n, dtype, filt=None):
+    nodes = []
+    src = "x"
+    if filt is not None:
+        nodes.append({"name": "k", "op": "filter", "src": "x", "pred": filt})
+        src = "k"
+    nodes.append({"name": "a", "op": "reduce", "src": src, "red": "avg"})
+    return {"inputs": [{"name": "x", "dtype": dtype, "n": n}], "nodes": nodes, "contracts": [], "outputs": ["a"]}
+
+
+def test_avg_closed_forms_and_empty():
+    for n in (1, 2, 999, 1000, 1 << 20):
+        x = np.arange(1, n + 1, dtype=np.float32)
+        r = oracle.evaluate(avg_spec(n, "f32"), {"x": x}).values["a"]
+        assert r["exact"] == (n + 1) / 2 and r["value"] == (n + 1) / 2  # exact in binary32
+        xi = np.arange(1, n + 1, dtype=np.int32)
+        ri = oracle.evaluate(avg_spec(n, "i32"), {"x": xi}).values["a"]
+        assert Fraction(ri["exact"]) == Fraction(n + 1, 2)
+    for dt, arr in (("f32", np.zeros(0, np.float32)), ("i32", np.zeros(0, np.int32))):
+        r = oracle.evaluate(avg_spec(0, dt), {"x": arr}).values["a"]
+        assert math.isnan(r["value"]) and math.isnan(r["exact"])
+    # everything filtered out: the mean of an empty collection
+    x = W.uniform_f32(1000, 5)
+    r = oracle.evaluate(avg_spec(1000, "f32", ["cmp", "gt", 2.0]), {"x": x}).values["a"]
+    assert math.isnan(r["value"])
+
+
+def test_avg_filtered_vs_fraction_mean():
+    x = W.normal_f32(5001, 6)
+    r = oracle.evaluate(avg_spec(5001, "f32", ["cmp", "gt", 0.25]), {"x": x}).values["a"]
+    kept = [Fraction(float(v)) for v in x if float(v) > float(np.float32(0.25))]
+    mean = sum(kept, Fraction(0)) / len(kept)
+    assert r["exact"] == float(mean)                      # correctly rounded float64 mean
+    assert abs(Fraction(r["value"]) - mean) <= Fraction(float(abs(np.float32(r["value"])))) / 2**23
+    assert r["abs_sum"] == float(sum((abs(k) for k in kept), Fraction(0)))
+    xi = W.uniform_i32(4003, 7, -10**6, 10**6)
+    ri = oracle.evaluate(avg_spec(4003, "i32", ["cmp", "lt", 0]), {"x": xi}).values["a"]
+    neg = [int(v) for v in xi.tolist() if v < 0]
+    assert ri["exact"] == float(Fraction(sum(neg), len(neg)))
