@@ -70,8 +70,18 @@ def cpu_baseline(n_sample: int) -> dict:
     dt = time.perf_counter() - t0
     cnt = ref.values["c"]["value"]
     algo = 12.0 * n_sample + 4.0 * cnt
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(algo / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"cfg2 chain + sortedness at n=2^{int(np.log2(n_sample))} ({dt:.1f} s, numpy float64, one thread)"}
+            "sample": f"cfg2 chain + sortedness at n=2^{int(np.log2(n_sample))} ({dt:.1f} s, numpy float64 "
+                      f"interpreter, one thread; host {model}, {os.cpu_count()} logical CPUs visible)"}
 
 
 def log(msg: str) -> None:
@@ -332,7 +342,7 @@ def main():
     ap.add_argument("--n", type=int, default=N_DEFAULT)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
-    ap.add_argument("--cpu-sample-log2", type=int, default=23)
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="run the context's default launch plan (no autotuning)")

@@ -111,6 +111,13 @@ sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll);
 sg_status sg_ctx_set_specialize(sg_ctx ctx, int on);
 /* Record the device time of every kernel launch with HIP events on the context stream. */
 sg_status sg_ctx_set_timing(sg_ctx ctx, int on);
+/* Spin limit of the kernels' bounded waits (compaction prefixes, result finalization): a
+ * wait that reaches it gives up, and the execution returns SG_E_DEVICE with the context's
+ * (or the batch's) kernel state cleared, so the next execution starts clean.  spins < 0
+ * restores the default (about 4 s); 0 makes every such wait give up at once, which lets the
+ * error path be exercised from the host.  Applies to later launches, including replays of
+ * batches created earlier. */
+sg_status sg_ctx_set_wait_limit(sg_ctx ctx, int64_t spins);
 /* Accumulated device time (ms) and launch count of one kernel family since the last reset:
  * "stream" (interpreter), "stream_spec" (specialized), "gemm", "product_check", "mlp_train",
  * "mlp_infer". */

@@ -73,7 +73,7 @@ def _sig(lib):
     sigs = {
         "sg_ctx_create": [c_int, H, P(H)], "sg_ctx_destroy": [H], "sg_ctx_set_mode": [H, c_int],
         "sg_ctx_set_fusion": [H, c_int], "sg_ctx_set_launch": [H, c_int, c_int], "sg_ctx_set_timing": [H, c_int],
-        "sg_ctx_set_specialize": [H, c_int],
+        "sg_ctx_set_specialize": [H, c_int], "sg_ctx_set_wait_limit": [H, c_int64],
         "sg_ctx_last_launch": [H, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int64)],
         "sg_ctx_timing": [H, c_char_p, P(c_double), P(c_int64)], "sg_ctx_timing_reset": [H],
         "sg_vector_wrap": [H, c_int, H, c_int64, P(H)], "sg_matrix_wrap": [H, c_int, H, c_int64, c_int64, P(H)],
@@ -419,6 +419,29 @@ class Program:
         return STATUS[st], [Verdict.from_buffer_copy(buf[i]) for i in range(min(nv.value, cap))]
 
 
+def _features_tensor(X, what: str):
+    """A feature matrix the MLP kernels may read: CUDA, float32, contiguous, n x 24."""
+    import torch
+    if not isinstance(X, torch.Tensor) or not X.is_cuda:
+        raise ValueError(f"{what}: X must be a CUDA tensor")
+    if X.dtype != torch.float32 or not X.is_contiguous():
+        raise ValueError(f"{what}: X must be contiguous float32")
+    if X.dim() != 2 or X.shape[1] != 24:
+        raise ValueError(f"{what}: X must be n x 24, got {tuple(X.shape)}")
+    return X
+
+
+def _target_tensor(T, n: int, what: str):
+    import torch
+    if not isinstance(T, torch.Tensor) or not T.is_cuda:
+        raise ValueError(f"{what}: T must be a CUDA tensor")
+    if T.dtype != torch.float32 or not T.is_contiguous():
+        raise ValueError(f"{what}: T must be contiguous float32")
+    if T.numel() != n:
+        raise ValueError(f"{what}: T has {T.numel()} entries for {n} samples")
+    return T
+
+
 class Mlp:
     """The 24-64-64-1 cost model (parameters in the C ABI's layout, 5825 floats)."""
     NPARAMS = 5825
@@ -444,6 +467,10 @@ class Mlp:
     def grad(self, X, T):
         """X, T: CUDA float32 tensors (B x 24, B).  Returns (loss, gradient as numpy)."""
         import numpy as np
+        _features_tensor(X, "grad")
+        _target_tensor(T, X.shape[0], "grad")
+        if not 1 <= X.shape[0] <= 128:
+            raise ValueError("grad: a batch holds 1 to 128 samples")
         g = np.empty(self.NPARAMS, np.float32)
         loss = c_double()
         _check(load().sg_mlp_grad(self.h, c_void_p(X.data_ptr()), c_void_p(T.data_ptr()), X.shape[0],
@@ -452,6 +479,8 @@ class Mlp:
 
     def train(self, X, T, batch: int = 128, epochs: int = 10, lr: float = 1e-3):
         import numpy as np
+        _features_tensor(X, "train")
+        _target_tensor(T, X.shape[0], "train")
         el = np.empty(epochs, np.float64)
         _check(load().sg_mlp_train(self.h, c_void_p(X.data_ptr()), c_void_p(T.data_ptr()), X.shape[0], batch,
                                    epochs, lr, el.ctypes.data_as(POINTER(c_double))), self.ctx.h)
@@ -459,6 +488,7 @@ class Mlp:
 
     def predict(self, X):
         import torch
+        _features_tensor(X, "predict")
         Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
         _check(load().sg_mlp_predict(self.h, c_void_p(X.data_ptr()), X.shape[0], c_void_p(Y.data_ptr())), self.ctx.h)
         torch.cuda.synchronize()
@@ -535,6 +565,10 @@ class Context:
 
     def set_timing(self, on: bool):
         _check(load().sg_ctx_set_timing(self.h, int(on)), self.h)
+
+    def set_wait_limit(self, spins: int = -1):
+        """Spin limit of the kernels' bounded waits (-1: default; 0: every wait gives up at once)."""
+        _check(load().sg_ctx_set_wait_limit(self.h, spins), self.h)
 
     def timing(self, kernel: str):
         ms, n = c_double(), c_int64()

@@ -21,6 +21,8 @@ using namespace sgrt;
 hipError_t sg_launch_stream(const StreamArgs& a, int unroll, bool inl, int grid, int block, size_t lds_bytes,
                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t sg_launch_epoch_bump(uint32_t* e, hipStream_t s);
+hipError_t sg_launch_set_word(uint32_t* p, uint32_t v, hipStream_t s);
+hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s);
 
 struct sg_batch_s {
     sg_ctx_s* ctx = nullptr;
@@ -34,6 +36,7 @@ struct sg_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     InstResult* host = nullptr;
+    uint32_t limit_set = 0;          // wait limit last written to the device word (raw form)
 };
 
 static sg_status batch_free(sg_batch_s* b) {
@@ -129,6 +132,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     a.tags = b->scratch.tags;
     a.lookback = b->scratch.lookback;
     a.epoch_ptr = b->scratch.epoch;
+    a.limit_ptr = b->scratch.epoch + 1;  // zeroed with the scratch: the default limit
     a.results = b->scratch.results;
     a.ninst = n;
     a.substeps = b->substeps;
@@ -163,6 +167,12 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
 sg_status sg_batch_launch(sg_batch b) {
     if (!b) return fail(nullptr, SG_E_INVALID, "batch_launch: NULL batch");
     sg_ctx_s* ctx = b->ctx;
+    // the spin limit lives in a device word that the kernel reads, so a graph replay sees a
+    // changed context setting; it is written outside the graph, on the same stream
+    if (ctx->wait_limit != b->limit_set) {
+        SG_HIP(ctx, sg_launch_set_word(b->scratch.epoch + 1, ctx->wait_limit, ctx->stream));
+        b->limit_set = ctx->wait_limit;
+    }
     if (b->exec) {
         SG_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
     } else {
@@ -183,7 +193,15 @@ sg_status sg_batch_run(sg_batch b, int32_t* status_out, sg_verdict* verdicts, in
                                ctx->stream));
     SG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int i = 0; i < n; ++i)
-        if (b->host[i].err) return fail(ctx, SG_E_DEVICE, "batched kernel reported a device-side failure");
+        if (b->host[i].err) {
+            // a wait that gave up leaves accumulators that late blocks added to after the
+            // finalization read them, and tags of this epoch: clear the batch's scratch (the
+            // epoch and limit words too) so that the next run starts from a clean state
+            (void)sg_launch_zero((uint64_t*)b->scratch.base, (int64_t)(b->scratch.bytes / 8), ctx->stream);
+            (void)hipStreamSynchronize(ctx->stream);
+            b->limit_set = 0;
+            return fail(ctx, SG_E_DEVICE, "batched kernel reported a device-side failure (a bounded wait timed out)");
+        }
     int32_t nv = 0;
     std::vector<sg_verdict> V;
     std::vector<InstResult> one(1);

@@ -26,6 +26,7 @@ hipError_t sg_launch_product_check(const float* C, const float* A, const float* 
                                    int64_t N, int64_t K, int64_t nvec, double tol, double* work, InstResult* res,
                                    hipStream_t s);
 int sg_stream_occupancy(int unroll, bool inl, int block, size_t lds_bytes);
+hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s);
 
 namespace sgrt {
 
@@ -369,6 +370,7 @@ sg_status launch_program(sg_program_s* P, ExecSlot& es) {
             a.lds_sums = jk ? 0 : ip.nsum;
             a.lds_cemit = inst_cemit(ip);
             a.epoch_val = next_epoch(ctx);
+            a.wait_limit = ctx->wait_limit;
             fill_inst(ip, a.inst0, 0, g.ntiles, 0);
             std::memcpy(a.prog0, ip.prog.data(), ip.prog.size() * sizeof(SgOp));
             const auto ev = t_launch(jk ? "stream_spec" : "stream");
@@ -447,7 +449,7 @@ sg_status finish_program(sg_program_s* P, ExecSlot& es, sg_verdict* verdicts, in
     for (int64_t i = 0; i < nres; ++i) {
         if (const uint32_t err = es.host[i].err) {
             // reset the state the kernels keep between launches, then report
-            (void)hipMemsetAsync(S.base, 0, S.bytes, ctx->stream);
+            (void)sg_launch_zero((uint64_t*)S.base, (int64_t)(S.bytes / 8), ctx->stream);
             (void)hipStreamSynchronize(ctx->stream);
             ctx->epoch = 0;
             return fail(ctx, SG_E_DEVICE,

@@ -230,6 +230,8 @@ sg_status sg_mlp_get_params(sg_mlp m, float* params, int64_t nparams) {
 sg_status sg_mlp_grad(sg_mlp m, const float* X_dev, const float* T_dev, int32_t B, float* grad_host, double* loss) {
     if (!m || !X_dev || !T_dev || B < 1 || B > sg::MB || !grad_host) return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_grad: bad argument (1 <= B <= 128)");
     sg_ctx_s* ctx = m->ctx;
+    if (sg_status st = check_device_range(ctx, X_dev, (size_t)B * sg::MI * 4, "mlp_grad X")) return st;
+    if (sg_status st = check_device_range(ctx, T_dev, (size_t)B * 4, "mlp_grad T")) return st;
     SG_HIP(ctx, hipFuncSetAttribute((const void*)sg::mlp_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)sizeof(sg::MlpLds)));
     hipLaunchKernelGGL(sg::mlp_grad_kernel, dim3(1), dim3(256), sizeof(sg::MlpLds), ctx->stream, m->P, m->P + sg::MP,
@@ -250,6 +252,8 @@ sg_status sg_mlp_train(sg_mlp m, const float* X_dev, const float* T_dev, int64_t
     if (!m || !X_dev || !T_dev || n < 1 || batch < 1 || batch > sg::MB || epochs < 1 || epochs > 1000)
         return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_train: bad argument");
     sg_ctx_s* ctx = m->ctx;
+    if (sg_status st = check_device_range(ctx, X_dev, (size_t)n * sg::MI * 4, "mlp_train X")) return st;
+    if (sg_status st = check_device_range(ctx, T_dev, (size_t)n * 4, "mlp_train T")) return st;
     sg::AdamArgs ad{lr, 0.9f, 0.999f, 1e-8f};
     const char* name = "mlp_train";
     static bool attr_set = false;
@@ -290,6 +294,8 @@ sg_status sg_mlp_predict(sg_mlp m, const float* X_dev, int64_t n, float* Y_dev) 
     if (!m || !X_dev || !Y_dev || n < 0) return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_predict: bad argument");
     if (n == 0) return SG_OK;
     sg_ctx_s* ctx = m->ctx;
+    if (sg_status st = check_device_range(ctx, X_dev, (size_t)n * sg::MI * 4, "mlp_predict X")) return st;
+    if (sg_status st = check_device_range(ctx, Y_dev, (size_t)n * 4, "mlp_predict Y")) return st;
     const unsigned grid = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(sg::mlp_predict_kernel, dim3(grid), dim3(256), 0, ctx->stream, m->P, X_dev, n, Y_dev);
     SG_HIP(ctx, hipGetLastError());

@@ -49,6 +49,29 @@ sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what) {
     return fail(ctx, SG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// A kernel handed a host address or a buffer shorter than its arguments say would fault the
+// GPU; the runtime knows the allocation that holds a device address, so the range is checked
+// before anything is launched on it.
+sg_status check_device_range(sg_ctx_s* ctx, const void* p, size_t bytes, const char* what) {
+    if (bytes == 0) return SG_OK;
+    if (!p) return fail(ctx, SG_E_INVALID, std::string(what) + ": NULL device pointer");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(ctx, SG_E_INVALID, std::string(what) + ": not a device address");
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, SG_E_INVALID, std::string(what) + ": address is in no device allocation");
+    }
+    const uintptr_t b = (uintptr_t)base, a = (uintptr_t)p;
+    if (a < b || a - b > size || bytes > size - (a - b))
+        return fail(ctx, SG_E_INVALID, std::string(what) + ": buffer extends past its device allocation");
+    return SG_OK;
+}
+
 // ---------------------------------------------------------------------------------------------
 // device memory
 
@@ -368,6 +391,13 @@ sg_status sg_ctx_set_specialize(sg_ctx ctx, int on) {
     return SG_OK;
 }
 
+sg_status sg_ctx_set_wait_limit(sg_ctx ctx, int64_t spins) {
+    if (!ctx) return SG_E_INVALID;
+    if (spins >= (int64_t)0xFFFFFFFEu) return fail(ctx, SG_E_INVALID, "wait limit: at most 2^32 - 2 spins");
+    ctx->wait_limit = spins < 0 ? 0u : (uint32_t)(spins + 1);
+    return SG_OK;
+}
+
 sg_status sg_ctx_set_timing(sg_ctx ctx, int on) {
     if (!ctx) return SG_E_INVALID;
     ctx->timing = on != 0;
@@ -422,6 +452,7 @@ sg_status sg_vector_wrap(sg_ctx ctx, sg_dtype dtype, void* dev, int64_t n, sg_no
     if (!ctx || !out || n < 0 || (!dev && n > 0)) return fail(ctx, SG_E_INVALID, "vector_wrap: bad argument");
     if (!valid_elem_dtype(dtype)) return fail(ctx, SG_E_DTYPE, "vector_wrap: dtype must be f32 or i32");
     if (n >= (int64_t)1 << 32) return fail(ctx, SG_E_INVALID, "vector_wrap: at most 2^32-1 elements");
+    if (sg_status st = check_device_range(ctx, dev, (size_t)n * 4, "vector_wrap")) return st;
     auto* nd = new_node(ctx, OPN_INPUT, dtype, n);
     nd->dev = dev;
     nd->space = 0;  // dense index space; filters open new ones

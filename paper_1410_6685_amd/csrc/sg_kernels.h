@@ -114,6 +114,10 @@ static_assert(sizeof(InstResult) == 256, "result size");
 
 enum ErrBits : uint32_t { ERR_LOOKBACK_TIMEOUT = 1u, ERR_FINALIZE_TIMEOUT = 2u };
 
+// Spins of a bounded wait before it gives up and reports a device error (each spin sleeps
+// about a microsecond).
+constexpr uint32_t kDefaultWaitSpins = 1u << 22;
+
 struct StreamArgs {
     const InstDesc* insts;      // batched launches: instance table (device)
     const SgOp* progs;          // batched launches: programs (device)
@@ -131,6 +135,8 @@ struct StreamArgs {
     int32_t lds_slots;          // per-lane exact accumulators kept in LDS (max over instances)
     int32_t lds_sums;           // per-lane float64 sums kept in LDS (max over instances)
     int32_t lds_cemit;          // compacted outputs staged in LDS (max over instances)
+    uint32_t wait_limit;        // spin limit of bounded waits: 0 default, k > 0: k - 1 spins
+    const uint32_t* limit_ptr;  // batched launches: the same limit in a device word (or null)
     InstDesc inst0;             // single-instance launches: the instance
     SgOp prog0[MAX_INLINE_OPS]; // single-instance launches: its program
 };

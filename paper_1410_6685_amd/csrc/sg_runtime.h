@@ -52,6 +52,7 @@ struct sg_ctx_s {
     int last_grid = 0, last_block = 0, last_unroll = 0, last_substeps = 0;  // last streaming launch
     size_t last_lds = 0;
     bool timing = false;
+    uint32_t wait_limit = 0;  // spin limit of the kernels' bounded waits (raw form, 0 = default)
     uint64_t next_id = 0;
     uint64_t generation = 0;  // bumped when a setting that changes plans changes
     std::string error;
@@ -181,6 +182,8 @@ struct ExecSlot {
 };
 
 sg_status fail(sg_ctx_s* ctx, sg_status st, const std::string& msg);
+// SG_OK when [p, p + bytes) lies inside one device allocation of the calling process
+sg_status check_device_range(sg_ctx_s* ctx, const void* p, size_t bytes, const char* what);
 sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what);
 void* dev_alloc(sg_ctx_s* ctx, size_t bytes);
 void dev_free(sg_ctx_s* ctx, void* p);

@@ -309,6 +309,12 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
     const uint32_t epoch = A.epoch_ptr
         ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(A.epoch_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         : A.epoch_val;
+    // spin limit of every bounded wait: a device word (batches: settable between graph
+    // replays) or the launch argument; raw 0 = the default, raw k = k - 1 spins (1: fail at once)
+    const uint32_t wraw = A.limit_ptr
+        ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(A.limit_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        : A.wait_limit;
+    const uint32_t wlimit = wraw == 0 ? kDefaultWaitSpins : wraw - 1u;
     const int spread = A.spread;
     const int sp_idx = (int)(blockIdx.x % (unsigned)spread);
     const kptr kargs = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
@@ -462,6 +468,10 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         const int64_t nq = INLINE ? (int64_t)gridDim.x : ntiles;
         const int64_t q0 = INLINE ? 0 : tile0;
         for (uint32_t spins = 0;; ++spins) {
+            if (spins >= wlimit) {  // bounded: report instead of hanging
+                if (tid == 0) atomicOr(&res->err, (uint32_t)ERR_FINALIZE_TIMEOUT);
+                break;
+            }
             int ok = 1;
             for (int64_t q = tid; q < nq; q += B)
                 for (int w = 0; w < words; ++w) {
@@ -470,10 +480,6 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                     ok &= (uint32_t)(x >> 32) == epoch;
                 }
             if (__syncthreads_and(ok)) break;
-            if (spins > (1u << 22)) {
-                if (tid == 0) atomicOr(&res->err, (uint32_t)ERR_FINALIZE_TIMEOUT);
-                break;
-            }
             __builtin_amdgcn_s_sleep(2);
         }
         for (int k = 0; k < nsum; ++k) {
@@ -532,6 +538,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         for (int64_t j0 = 0; j0 == 0 || j0 < b; j0 += 64 * LB_WINDOW) {
             const bool want_base = j0 == 0 && r > 0;
             for (;;) {
+                if (spins >= wlimit) { excl = -1; break; }
                 const uint64_t bd = want_base ? ld_relaxed(&rbase[r]) : (LB_AGG | lb_epoch);
                 uint64_t d[LB_WINDOW];
 #pragma unroll
@@ -550,7 +557,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                     excl += (int64_t)(uint32_t)bd + wave_sum_i64(part);  // a base that was not loaded adds 0
                     break;
                 }
-                if (++spins > (1u << 22)) { excl = -1; break; }
+                ++spins;
                 __builtin_amdgcn_s_sleep(1);
             }
             if (excl < 0) break;
@@ -573,6 +580,11 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             // descriptors at distance p + 1 = 1 + 64m + lane, nearest first
             int64_t j = pend - 1;
             for (uint32_t spins = 0;;) {
+                if (spins >= wlimit) {
+                    if (lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
+                    excl = -1;  // no prefix: nothing of this tile is written
+                    break;
+                }
                 uint64_t d[LB_WINDOW];
 #pragma unroll
                 for (int m = 0; m < LB_WINDOW; ++m) {
@@ -594,11 +606,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                     }
                 }
                 if (wait) {
-                    if (++spins > (1u << 22)) {
-                        if (lane == 0) atomicOr(&A.results[cur].err, (uint32_t)ERR_LOOKBACK_TIMEOUT);
-                        excl = -1;  // no prefix: nothing of this tile is written
-                        break;
-                    }
+                    ++spins;
                     __builtin_amdgcn_s_sleep(1);
                     continue;
                 }
@@ -960,6 +968,9 @@ __global__ void zero_kernel(uint64_t* p, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
 }
+
+// set one 32-bit device word (one thread), so the call can sit in a stream a graph replays on
+__global__ void set_word_kernel(uint32_t* p, uint32_t v) { *p = v; }
 
 // advance the launch epoch of a captured graph (one thread)
 __global__ void epoch_bump_kernel(uint32_t* e) {

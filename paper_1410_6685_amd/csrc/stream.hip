@@ -38,6 +38,11 @@ extern "C++" hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+extern "C++" hipError_t sg_launch_set_word(uint32_t* p, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(sg::set_word_kernel, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
 extern "C++" hipError_t sg_launch_epoch_bump(uint32_t* e, hipStream_t s) {
     hipLaunchKernelGGL(sg::epoch_bump_kernel, dim3(1), dim3(1), 0, s, e);
     return hipGetLastError();

@@ -202,3 +202,41 @@ def test_compaction_many_rounds(sg, ctx, plan):
     say("compaction plan", plan)
     status, verdicts = built.program.execute()
     compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
+
+
+@pytest.mark.parametrize("seed", [3, 11, 19, 27, 35, 43])
+def test_random_chains_non_dyadic_constants(sg, ctx, seed):
+    """Seeded chains whose affine constants are not dyadic (a*x is inexact): an FMA contracted
+    across the multiply and the add would change their bits, on either kernel."""
+    n = 40_000 + 977 * seed
+    spec = W.random_chain_spec(n, 5000 + seed)
+    inp = W.cfg4_instance_inputs(spec, 7000 + seed)
+    built, status, verdicts, _ = run_spec(sg, ctx, spec, inp)
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 5, 8, 13, 21, 34, 55])
+def test_selector_chains_both_kernels(sg, ctx, seed):
+    n = 30_011 + 131 * seed
+    spec = W.selector_chain_spec(n, 9000 + seed)
+    if spec["inputs"][0]["dtype"] == "f32":
+        inp = {i["name"]: W.uniform_f32(n, 100 * seed + k) for k, i in enumerate(spec["inputs"])}
+    else:
+        inp = {i["name"]: W.uniform_i32(n, 100 * seed + k, -50000, 50000) for k, i in enumerate(spec["inputs"])}
+    built, status, verdicts, _ = run_spec(sg, ctx, spec, inp)
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
+
+
+def test_affine_is_not_contracted(sg, ctx):
+    """0.3x + 0.7 with x chosen so that RN(RN(0.3x) + 0.7) differs from RN(0.3x + 0.7) (one
+    rounding, a fused multiply-add) on many elements: the chain must round twice."""
+    x = W.uniform_f32(1 << 16, 99, -4.0, 4.0)
+    a, b = np.float32(0.3), np.float32(0.7)
+    two = (a * x) + b
+    one = (x.astype(np.float64) * np.float64(a) + np.float64(b)).astype(np.float32)
+    assert np.count_nonzero(two != one) > 1000  # the test data separates the two roundings
+    spec = {"inputs": [{"name": "x", "dtype": "f32", "n": x.size}],
+            "nodes": [{"name": "u", "op": "map", "src": "x", "fn": ["affine", 0.3, 0.7]}], "contracts": [],
+            "outputs": ["u"]}
+    built, status, verdicts, _ = run_spec(sg, ctx, spec, {"x": x})
+    assert np.array_equal(built["u"].to_host().view(np.uint32), two.view(np.uint32))
