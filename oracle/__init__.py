@@ -15,11 +15,12 @@ Parity status per function (what pins each one) is listed in ``oracle/PINS.md``.
 from .elem import exp_rn32, apply_fn, eval_pred, wrap_i32
 from .reduce import exact_sum, fmax_total, fmin_total, for_all, exists, is_sorted
 from .matrix import matmul64, product_check
+from .sort import quicksort
 from . import mlp
 from .interp import evaluate, OracleResult, STATUS
 
 __all__ = [
     "exp_rn32", "apply_fn", "eval_pred", "wrap_i32",
     "exact_sum", "fmax_total", "fmin_total", "for_all", "exists", "is_sorted",
-    "matmul64", "product_check", "evaluate", "OracleResult", "STATUS",
+    "matmul64", "product_check", "quicksort", "evaluate", "OracleResult", "STATUS",
 ]

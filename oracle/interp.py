@@ -23,6 +23,7 @@ import numpy as np
 from .elem import apply_fn, eval_pred
 from .reduce import exact_sum, exact_sum_f32, abs_sum, fmax_total, fmin_total, for_all, exists, is_sorted
 from .matrix import matmul64, product_check
+from .sort import quicksort
 
 STATUS = {"ok": 0, "pre_violated": 16, "post_violated": 17}
 MODES = ("off", "pre", "pre_post")
@@ -151,6 +152,20 @@ def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
             r = _reduce(nd["red"], vals[nd["src"]].reshape(-1), src["dtype"])
             tab[nd["name"]] = {"kind": "scalar", "dtype": r["dtype"], "shape": ()}
             vals[nd["name"]] = r
+        elif op == "concat":
+            # Table 2 concatenate: the items of a followed by those of b
+            a, b = tab[nd["a"]], tab[nd["b"]]
+            if a["dtype"] != b["dtype"]:
+                raise ShapeError("concatenate needs operands of one element type")
+            v = np.concatenate([vals[nd["a"]].reshape(-1), vals[nd["b"]].reshape(-1)])
+            tab[nd["name"]] = {"kind": "coll", "dtype": a["dtype"], "shape": (v.size,)}
+            vals[nd["name"]] = v
+        elif op == "qsort":
+            # Section 4 quicksort (Listing 3) of a vector
+            src = tab[nd["src"]]
+            v = quicksort(vals[nd["src"]].reshape(-1))
+            tab[nd["name"]] = {"kind": "coll", "dtype": src["dtype"], "shape": (v.size,)}
+            vals[nd["name"]] = v
         elif op == "matmul":
             a, b = tab[nd["a"]], tab[nd["b"]]
             if len(a["shape"]) != 2 or len(b["shape"]) != 2 or a["shape"][1] != b["shape"][0]:
@@ -187,6 +202,12 @@ def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
             dev = abs(s["value"] - s["exact"])
             bound = c.get("abs_tol", 0.0) + c.get("rel_tol", 0.0) * asum
             return Verdict(int(dev <= bound), -1, dev)
+        if chk == "count_eq":
+            # scalar contract Result.count = old a.count (Listing 3): the operands are never
+            # changed by the body, so the old count is the count
+            ca = vals[c["node"]].size
+            cb = vals[c["other"]].size
+            return Verdict(int(ca == cb), -1, float(ca - cb))
         if chk == "product":
             Cv = vals[c["node"]]
             if node.get("reference64"):

@@ -76,3 +76,38 @@ def test_postcondition_holds_on_seeded_inputs(kind):
     # the same multiset: every value keeps its number of occurrences
     assert np.array_equal(np.unique(x.view(np.uint32), return_counts=True)[1],
                           np.unique(y.view(np.uint32), return_counts=True)[1])
+
+
+def qs_spec(n, dtype="f32"):
+    return {"inputs": [{"name": "a", "dtype": dtype, "n": n}],
+            "nodes": [{"name": "r", "op": "qsort", "src": "a"}],
+            "contracts": [{"kind": "ensure", "check": "sorted", "node": "r"},
+                          {"kind": "ensure", "check": "count_eq", "node": "r", "other": "a"}],
+            "outputs": ["r"]}
+
+
+def test_listing3_contracts_through_the_interpreter():
+    import oracle
+    x = W.normal_f32(5000, 9)
+    r = oracle.evaluate(qs_spec(5000), {"a": x})
+    assert r.status == "ok" and [v.holds for v in r.verdicts] == [1, 1]
+    y = x.copy()
+    y[[10, 4000]] = np.nan  # dropped by every filter: count = old count fails
+    r = oracle.evaluate(qs_spec(5000), {"a": y})
+    assert r.status == "post_violated" and r.violated == 1
+    assert r.verdicts[0].holds == 1 and r.verdicts[1].measure == -2.0
+
+
+def test_concatenate_is_items_of_a_then_b():
+    import oracle
+    a, b = W.uniform_f32(37, 1), W.uniform_f32(0, 2)
+    c = W.uniform_f32(5, 3)
+    spec = {"inputs": [{"name": "a", "dtype": "f32", "n": 37}, {"name": "b", "dtype": "f32", "n": 0},
+                       {"name": "c", "dtype": "f32", "n": 5}],
+            "nodes": [{"name": "k", "op": "filter", "src": "a", "pred": ["cmp", "gt", 0.0]},
+                      {"name": "ab", "op": "concat", "a": "k", "b": "b"},
+                      {"name": "abc", "op": "concat", "a": "ab", "b": "c"}],
+            "contracts": [], "outputs": ["abc"]}
+    r = oracle.evaluate(spec, {"a": a, "b": b, "c": c})
+    want = [v for v in a.tolist() if v > 0.0] + c.tolist()
+    assert r.values["abc"].tolist() == want
