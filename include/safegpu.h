@@ -87,7 +87,7 @@ typedef struct sg_verdict {
 } sg_verdict;
 
 enum { SG_CHECK_FOR_ALL = 0, SG_CHECK_EXISTS = 1, SG_CHECK_SORTED = 2, SG_CHECK_CLOSE = 3,
-       SG_CHECK_PRODUCT = 4 };
+       SG_CHECK_PRODUCT = 4, SG_CHECK_COUNT_EQ = 5 };
 
 /* ---- context ---------------------------------------------------------------------------- */
 
@@ -169,6 +169,16 @@ sg_status sg_zip(sg_node a, sg_node b, sg_binop op, sg_node* out);        /* plu
 sg_status sg_filter(sg_node in, sg_pred p, sg_node* out);                 /* stable */
 sg_status sg_reduce(sg_node in, sg_red red, sg_node* out);                /* scalar node */
 sg_status sg_matmul(sg_node A, sg_node B, sg_node* out);                  /* FP32 matrix cores */
+/* concatenate (Table 2): the items of a followed by those of b (same element type; vectors).
+ * Capacity a.capacity + b.capacity; count a.count + b.count. */
+sg_status sg_concat(sg_node a, sg_node b, sg_node* out);
+/* The quicksort of Section 4 (Listing 3) on an f32 or i32 vector: pivot = the item at index
+ * count / 2, three stable filters (less, equal, greater), result = quicksort(less) ++ equal ++
+ * quicksort(greater), run level by level on the GPU.  Items no filter keeps (NaN items, or all
+ * items of a collection whose pivot is NaN) are dropped, as in the listing, so the result's
+ * count can be smaller than the input's: attach sg_program_count_eq to check it.  Capacity =
+ * the input's capacity. */
+sg_status sg_quicksort(sg_node in, sg_node* out);
 sg_status sg_release(sg_node n);
 
 /* ---- programs: roots plus require/ensure clauses ---------------------------------------- */
@@ -185,6 +195,10 @@ sg_status sg_program_close(sg_program p, sg_clause kind, sg_node s, double abs_t
 /* Product check of C = A B with the nvec x N matrix R of probe vectors (one per row):
  * |C r - A(B r)|_i <= (gamma_2K + 2^-40) (|A|(|B||r|))_i for every probe and row. */
 sg_status sg_program_product(sg_program p, sg_clause kind, sg_node C, sg_node A, sg_node B, sg_node R, int32_t* id);
+/* Scalar contract count(n) = old count(other) (the postcondition Result.count = a.count of
+ * Listing 3).  The operands are never changed by a program, so the old count is the count
+ * before or after the body alike.  Evaluated after the body; measure = count(n) - count(other). */
+sg_status sg_program_count_eq(sg_program p, sg_clause kind, sg_node n, sg_node other, int32_t* id);
 /* Mark `n` as a fusion split point: it is materialized and its consumers start a new pass. */
 sg_status sg_program_split(sg_program p, sg_node n);
 /* Run the program (trigger "update").  Writes up to `cap` verdicts.  Returns SG_OK,
@@ -214,6 +228,10 @@ sg_status sg_scalar_get(sg_node s, double* f, int64_t* i);
 /* float64 shadow of a float sum or avg node (accumulated in float64 in the same pass). */
 sg_status sg_scalar_shadow(sg_node s, double* f64);
 sg_status sg_count(sg_node c, int64_t* n);
+/* item (Table 2): the item at 0-based index i (executes the collection if needed); f = its
+ * value as double, iv = as integer (i32 collections).  Built-in precondition 0 <= i < count,
+ * else SG_E_INVALID. */
+sg_status sg_item(sg_node c, int64_t i, double* f, int64_t* iv);
 /* Copy a collection to host memory (at most cap elements); *n = its count. */
 sg_status sg_to_host(sg_node c, void* dst, int64_t cap, int64_t* n);
 /* Device address and count of a computed collection (valid until the node is released or

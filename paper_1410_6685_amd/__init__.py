@@ -27,7 +27,7 @@ CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5}
 BINOP = {"add": 0, "sub": 1, "mul": 2}
 RED = {"sum": 0, "min": 1, "max": 2, "avg": 3, "count": 4}
 CLAUSE = {"require": 0, "ensure": 1}
-CHECKS = {0: "for_all", 1: "exists", 2: "sorted", 3: "close", 4: "product"}
+CHECKS = {0: "for_all", 1: "exists", 2: "sorted", 3: "close", 4: "product", 5: "count_eq"}
 
 
 class Plan(ctypes.Structure):
@@ -85,7 +85,8 @@ def _sig(lib):
         "sg_pred_true": [P(H)], "sg_pred_and": [H, H, P(H)], "sg_pred_or": [H, H, P(H)], "sg_pred_not": [H, P(H)],
         "sg_pred_release": [H],
         "sg_map": [H, H, P(H)], "sg_zip": [H, H, c_int, P(H)], "sg_filter": [H, H, P(H)], "sg_reduce": [H, c_int, P(H)],
-        "sg_matmul": [H, H, P(H)], "sg_release": [H],
+        "sg_matmul": [H, H, P(H)], "sg_release": [H], "sg_concat": [H, H, P(H)], "sg_quicksort": [H, P(H)],
+        "sg_item": [H, c_int64, P(c_double), P(c_int64)], "sg_program_count_eq": [H, c_int, H, H, P(c_int32)],
         "sg_program_create": [H, P(H)], "sg_program_add_root": [H, H],
         "sg_program_quant": [H, c_int, c_int, H, H, P(c_int32)], "sg_program_sorted": [H, c_int, H, P(c_int32)],
         "sg_program_close": [H, c_int, H, c_double, c_double, P(c_int32)],
@@ -282,6 +283,20 @@ class Node:
     def matmul(self, other: "Node"):
         return self._new(load().sg_matmul, self.h, other.h)
 
+    def concat(self, other: "Node"):
+        """concatenate: the items of this collection followed by those of `other`."""
+        return self._new(load().sg_concat, self.h, other.h)
+
+    def quicksort(self):
+        """The quicksort of the collection API (pivot at count // 2, three stable filters)."""
+        return self._new(load().sg_quicksort, self.h)
+
+    def item(self, i: int):
+        """The item at 0-based index i (float for f32 collections, int for i32)."""
+        f, iv = c_double(), c_int64()
+        _check(load().sg_item(self.h, i, byref(f), byref(iv)), self.ctx.h)
+        return f.value, iv.value
+
     def scalar(self):
         f, i = c_double(), c_int64()
         _check(load().sg_scalar_get(self.h, byref(f), byref(i)), self.ctx.h)
@@ -356,6 +371,13 @@ class Program:
         cid = c_int32()
         _check(load().sg_program_product(self.h, CLAUSE[clause], C.h, A.h, B.h, R.h, byref(cid)), self.ctx.h)
         self._keep += [C, A, B, R]
+        return cid.value
+
+    def count_eq(self, clause: str, n: Node, other: Node) -> int:
+        """Scalar contract count(n) = old count(other)."""
+        cid = c_int32()
+        _check(load().sg_program_count_eq(self.h, CLAUSE[clause], n.h, other.h, byref(cid)), self.ctx.h)
+        self._keep += [n, other]
         return cid.value
 
     def split(self, n: Node):
@@ -645,6 +667,10 @@ def build_spec(ctx: Context, spec: dict, tensors: dict) -> Built:
             nodes[nd["name"]] = nodes[nd["src"]].reduce(nd["red"])
         elif op == "matmul":
             nodes[nd["name"]] = nodes[nd["a"]].matmul(nodes[nd["b"]])
+        elif op == "concat":
+            nodes[nd["name"]] = nodes[nd["a"]].concat(nodes[nd["b"]])
+        elif op == "qsort":
+            nodes[nd["name"]] = nodes[nd["src"]].quicksort()
         else:
             raise ValueError(op)
     prog = Program(ctx)
@@ -661,6 +687,8 @@ def build_spec(ctx: Context, spec: dict, tensors: dict) -> Built:
             ids.append(prog.close(c["kind"], nodes[c["node"]], float(c.get("abs_tol", 0.0)), float(c.get("rel_tol", 0.0))))
         elif chk == "product":
             ids.append(prog.product(c["kind"], nodes[c["node"]], nodes[c["a"]], nodes[c["b"]], nodes[c["r"]]))
+        elif chk == "count_eq":
+            ids.append(prog.count_eq(c["kind"], nodes[c["node"]], nodes[c["other"]]))
         else:
             raise ValueError(chk)
     return Built(ctx, nodes, prog, ids)

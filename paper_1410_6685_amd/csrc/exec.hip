@@ -242,6 +242,25 @@ sg_status assemble_verdicts(sg_program_s* P, const InstResult* results, std::vec
             }
         }
     }
+    // count = old count: counts after the body (operands are never changed by a program)
+    auto count_of = [&](const sg_node_s* x) -> int64_t {
+        if (is_kernel_node(x)) return x->op == OPN_MATMUL ? x->n : x->count;
+        for (auto& ip : plan.insts)
+            for (auto* o : ip.outs)
+                if (o == x) {
+                    const InstResult& r = results[ip.result_index];
+                    if (std::find(ip.compacted.begin(), ip.compacted.end(), x) != ip.compacted.end()) return r.scan_count;
+                    return ip.base_count_slot >= 0 ? r.slot[ip.base_count_slot] : x->n;
+                }
+        return x->op == OPN_INPUT ? x->n : x->count;
+    };
+    for (int ci : plan.active) {
+        const Contract& c = P->contracts[ci];
+        if (c.check != SG_CHECK_COUNT_EQ) continue;
+        const int64_t a = count_of(c.node), b = count_of(c.a);
+        V[ci].holds = a == b ? 1 : 0;
+        V[ci].measure = (double)(a - b);
+    }
     for (int ci = 0; ci < nc; ++ci) {
         if (plan.prod_result.size() <= (size_t)ci || plan.prod_result[ci] < 0) continue;
         const InstResult& r = results[plan.prod_result[ci]];
@@ -318,9 +337,12 @@ sg_status launch_program(sg_program_s* P, ExecSlot& es) {
         }
         max_tiles = std::max(max_tiles, g.ntiles);
     }
-    int nprod = 0;
-    for (auto& st : plan.steps) nprod += st.kind == Step::PRODUCT;
-    const int64_t nres = (int64_t)plan.insts.size() + nprod;
+    int nprod = 0, nnode = 0;
+    for (auto& st : plan.steps) {
+        nprod += st.kind == Step::PRODUCT;
+        nnode += st.kind == Step::NODE;
+    }
+    const int64_t nres = (int64_t)plan.insts.size() + nprod + nnode;
     for (auto& ip : plan.insts)
         if (ip.result_index < 0 || ip.result_index >= nres) return fail(ctx, SG_E_UNSUPPORTED, "plan result index out of range");
     // look-back words: one per tile, then one per round (round bases)
@@ -351,6 +373,7 @@ sg_status launch_program(sg_program_s* P, ExecSlot& es) {
 
     plan.prod_result.assign(P->contracts.size(), -1);
     int next_prod = (int)plan.insts.size();
+    int next_node = (int)plan.insts.size() + nprod;
     for (auto& step : plan.steps) {
         if (step.kind == Step::STREAM) {
             InstPlan& ip = plan.insts[step.inst];
@@ -382,6 +405,13 @@ sg_status launch_program(sg_program_s* P, ExecSlot& es) {
             ctx->last_substeps = g.C;
             ctx->last_lds = g.lds;
             for (auto* o : ip.compacted) o->count_dev = &S.results[ip.result_index].scan_count;
+        } else if (step.kind == Step::NODE) {
+            sg_node_s* nd = step.node;
+            if ((st = alloc_output(ctx, nd)) != SG_OK) return st;
+            t_begin(nd->op == OPN_QSORT ? "quicksort" : "concat");
+            st = run_node_step(ctx, plan, nd, S.results, S.results + next_node++);
+            t_end();
+            if (st != SG_OK) return st;
         } else if (step.kind == Step::GEMM) {
             sg_node_s* C = step.C;
             if ((st = alloc_output(ctx, C)) != SG_OK) return st;
@@ -467,6 +497,7 @@ sg_status finish_program(sg_program_s* P, ExecSlot& es, sg_verdict* verdicts, in
     for (auto& ip : plan.insts) publish_inst(ip, es.host[ip.result_index], publish);
     for (auto& step : plan.steps)
         if (step.kind == Step::GEMM) step.C->state = publish ? ST_COMPUTED : ST_UNPUBLISHED;
+        else if (step.kind == Step::NODE) step.node->state = publish ? ST_COMPUTED : ST_UNPUBLISHED;
     if (nverdicts) *nverdicts = nc;
     if (verdicts)
         for (int i = 0; i < nc && i < cap; ++i) verdicts[i] = V[i];
@@ -580,6 +611,18 @@ sg_status sg_program_product(sg_program p, sg_clause kind, sg_node C, sg_node A,
     c.a = A;
     c.b = B;
     c.r = R;
+    return add_contract(p, c, id);
+}
+
+sg_status sg_program_count_eq(sg_program p, sg_clause kind, sg_node n, sg_node other, int32_t* id) {
+    if (!p || !n || !other) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "count_eq: NULL argument");
+    if (!is_collection(n) || !is_collection(other)) return fail(p->ctx, SG_E_INVALID, "count_eq: operands must be collections");
+    if (n->ctx != p->ctx || other->ctx != p->ctx) return fail(p->ctx, SG_E_INVALID, "count_eq: node of another context");
+    sgrt::Contract c;
+    c.kind = kind;
+    c.check = SG_CHECK_COUNT_EQ;
+    c.node = n;
+    c.a = other;
     return add_contract(p, c, id);
 }
 
@@ -713,6 +756,29 @@ sg_status sg_to_host(sg_node c, void* dst, int64_t cap, int64_t* n) {
         SG_HIP(c->ctx, hipStreamSynchronize(c->ctx->stream));
     }
     if (n) *n = c->count;
+    return SG_OK;
+}
+
+sg_status sg_item(sg_node c, int64_t i, double* f, int64_t* iv) {
+    if (!c) return fail(nullptr, SG_E_INVALID, "item: NULL node");
+    if (!is_collection(c)) return fail(c->ctx, SG_E_INVALID, "item: not a collection");
+    sg_status st = trigger(c);
+    if (st != SG_OK) return st;
+    if (i < 0 || i >= c->count) return fail(c->ctx, SG_E_INVALID, "item: index out of range (0 <= i < count)");
+    if (!c->dev) return fail(c->ctx, SG_E_STATE, "item: collection has no storage");
+    uint32_t bits = 0;
+    SG_HIP(c->ctx, hipMemcpyAsync(&bits, (const char*)c->dev + (size_t)i * 4, 4, hipMemcpyDeviceToHost, c->ctx->stream));
+    SG_HIP(c->ctx, hipStreamSynchronize(c->ctx->stream));
+    if (c->dtype == SG_F32) {
+        float v;
+        std::memcpy(&v, &bits, 4);
+        if (f) *f = (double)v;
+        if (iv) *iv = 0;
+    } else {
+        const int32_t v = (int32_t)bits;
+        if (f) *f = (double)v;
+        if (iv) *iv = v;
+    }
     return SG_OK;
 }
 

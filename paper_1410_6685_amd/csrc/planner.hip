@@ -37,7 +37,7 @@ struct DSU {
 };
 
 bool is_source_node(const sg_node_s* n, const std::set<sg_node_s*>& mat) {
-    return n->op == OPN_INPUT || n->op == OPN_MATMUL || mat.count(const_cast<sg_node_s*>(n)) > 0;
+    return n->op == OPN_INPUT || is_kernel_node(n) || mat.count(const_cast<sg_node_s*>(n)) > 0;
 }
 
 bool active_contract(const Contract& c, sg_mode mode) {
@@ -77,7 +77,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
     // mat: written to memory; cut: consumers read it from memory in a later pass
     std::set<sg_node_s*> mat, cut;
     for (auto* r : P->roots)
-        if (is_collection(r) && r->op != OPN_INPUT && r->op != OPN_MATMUL) mat.insert(r);
+        if (is_collection(r) && r->op != OPN_INPUT && !is_kernel_node(r)) mat.insert(r);
     for (auto* s : P->splits)
         if (needed.count(s) && is_collection(s) && is_elementwise(s)) { mat.insert(s); cut.insert(s); }
     if (P->plan_split && needed.count(P->plan_split) && is_collection(P->plan_split) && is_elementwise(P->plan_split)) {
@@ -85,9 +85,9 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         cut.insert(P->plan_split);
     }
     for (auto* n : needed) {
-        if (n->op == OPN_MATMUL) {
+        if (is_kernel_node(n)) {  // its step reads its operands from memory
             for (auto* o : n->src)
-                if (is_elementwise(o)) mat.insert(o);
+                if (o && is_elementwise(o)) mat.insert(o);
         }
         if (!fused && is_elementwise(n) && is_collection(n)) { mat.insert(n); cut.insert(n); }
     }
@@ -137,7 +137,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         std::map<int, int> vcontract;  // contract -> vertex
         for (int ci : plan->active) {
             const Contract& c = P->contracts[ci];
-            if (c.check == SG_CHECK_PRODUCT) continue;
+            if (c.check == SG_CHECK_PRODUCT || c.check == SG_CHECK_COUNT_EQ) continue;  // not in a pass
             int v = dsu.add();
             vcontract[ci] = v;
             sg_node_s* t = c.node;
@@ -172,7 +172,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 if (!x) return false;
                 auto it = comp_of.find(x);
                 if (it != comp_of.end()) return it->second == from;
-                if (x->op == OPN_MATMUL) return made_in(x->src[0], from) || made_in(x->src[1], from);
+                if (is_kernel_node(x)) return made_in(x->src[0], from) || made_in(x->src[1], from);
                 return false;
             };
             // does component `to` read (transitively) what component `from` writes?
@@ -575,9 +575,9 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         if (resplit) continue;
 
         // ---- steps in dependency order -------------------------------------------------
-        std::vector<sg_node_s*> mm;
+        std::vector<sg_node_s*> mm;  // kernel nodes: matrix products, sorts, concatenations
         for (auto* n : needed)
-            if (n->op == OPN_MATMUL) mm.push_back(n);
+            if (is_kernel_node(n)) mm.push_back(n);
         std::sort(mm.begin(), mm.end(), [](sg_node_s* a, sg_node_s* b) { return a->id < b->id; });
         std::vector<int> prods;
         for (int ci : plan->active)
@@ -586,7 +586,10 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         const int NI = (int)plan->insts.size(), NM = (int)mm.size(), NP = (int)prods.size();
         std::vector<std::vector<sg_node_s*>> deps(NI + NM + NP);
         for (int i = 0; i < NI; ++i) deps[i] = inst_srcs[i];
-        for (int j = 0; j < NM; ++j) deps[NI + j] = {mm[j]->src[0], mm[j]->src[1]};
+        for (int j = 0; j < NM; ++j) {
+            for (auto* o : mm[j]->src)
+                if (o) deps[NI + j].push_back(o);
+        }
         for (int k = 0; k < NP; ++k) {
             const Contract& c = P->contracts[prods[k]];
             deps[NI + NM + k] = {c.node, c.a, c.b, c.r};
@@ -608,7 +611,11 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                 if (!ready) continue;
                 Step st;
                 if (it < NI) { st.kind = Step::STREAM; st.inst = it; }
-                else if (it < NI + NM) { st.kind = Step::GEMM; st.A = mm[it - NI]->src[0]; st.B = mm[it - NI]->src[1]; st.C = mm[it - NI]; }
+                else if (it < NI + NM && mm[it - NI]->op == OPN_MATMUL) {
+                    st.kind = Step::GEMM; st.A = mm[it - NI]->src[0]; st.B = mm[it - NI]->src[1]; st.C = mm[it - NI];
+                } else if (it < NI + NM) {
+                    st.kind = Step::NODE; st.node = mm[it - NI];
+                }
                 else {
                     const Contract& c = P->contracts[prods[it - NI - NM]];
                     st.kind = Step::PRODUCT; st.C = c.node; st.A = c.a; st.B = c.b; st.R = c.r; st.contract = prods[it - NI - NM];

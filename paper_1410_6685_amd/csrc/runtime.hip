@@ -644,6 +644,32 @@ sg_status sg_matmul(sg_node A, sg_node B, sg_node* out) {
     return SG_OK;
 }
 
+sg_status sg_concat(sg_node a, sg_node b, sg_node* out) {
+    sg_ctx_s* ctx = a ? a->ctx : (b ? b->ctx : nullptr);
+    if (!a || !b || !out) return fail(ctx, SG_E_INVALID, "concat: NULL argument");
+    if (a->ctx != b->ctx) return fail(ctx, SG_E_INVALID, "concat: operands of different contexts");
+    if (!is_collection(a) || !is_collection(b)) return fail(ctx, SG_E_INVALID, "concat: operand is a scalar");
+    if (a->dtype != b->dtype) return fail(ctx, SG_E_DTYPE, "concat: operands differ in element type");
+    if (a->n + b->n >= (int64_t)1 << 32) return fail(ctx, SG_E_INVALID, "concat: at most 2^32-1 elements");
+    auto* nd = new_node(ctx, OPN_CONCAT, a->dtype, a->n + b->n);
+    nd->src[0] = a; retain(a);
+    nd->src[1] = b; retain(b);
+    nd->space = nd->id;  // its count is known on the device only: a compacted collection
+    *out = nd;
+    return SG_OK;
+}
+
+sg_status sg_quicksort(sg_node in, sg_node* out) {
+    if (!in || !out) return fail(in ? in->ctx : nullptr, SG_E_INVALID, "quicksort: NULL argument");
+    if (!is_collection(in)) return fail(in->ctx, SG_E_INVALID, "quicksort: operand is a scalar");
+    if (in->dtype != SG_F32 && in->dtype != SG_I32) return fail(in->ctx, SG_E_DTYPE, "quicksort: f32 or i32 vectors");
+    auto* nd = new_node(in->ctx, OPN_QSORT, in->dtype, in->n);
+    nd->src[0] = in; retain(in);
+    nd->space = nd->id;  // dropped items make the count device-side
+    *out = nd;
+    return SG_OK;
+}
+
 sg_status sg_release(sg_node n) {
     if (!n) return SG_E_INVALID;
     release(n);

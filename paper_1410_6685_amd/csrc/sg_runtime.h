@@ -14,7 +14,8 @@
 
 namespace sgrt {
 
-enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL };
+// OPN_MATMUL and later: "kernel nodes", computed by a step of their own (not a streaming pass)
+enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL, OPN_QSORT, OPN_CONCAT };
 enum NodeState { ST_NONE = 0, ST_COMPUTED = 1, ST_UNPUBLISHED = 2 };
 enum FnKind { FK_AFFINE = 0, FK_ADDC, FK_MULC, FK_UNARY, FK_COMPOSE };
 enum PredKind { PK_CMP = 0, PK_FINITE, PK_RANGE, PK_TRUE, PK_AND, PK_OR, PK_NOT };
@@ -148,10 +149,11 @@ struct InstPlan {
 };
 
 struct Step {
-    enum Kind { STREAM = 0, GEMM = 1, PRODUCT = 2 } kind = STREAM;
+    enum Kind { STREAM = 0, GEMM = 1, PRODUCT = 2, NODE = 3 } kind = STREAM;
     int inst = -1;                           // STREAM
     sg_node_s *A = nullptr, *B = nullptr, *C = nullptr, *R = nullptr;  // GEMM / PRODUCT
     int contract = -1;                       // PRODUCT
+    sg_node_s* node = nullptr;               // NODE: the kernel node it computes
 };
 
 struct Plan {
@@ -222,6 +224,8 @@ void release(sg_node_s* n);
 void release(sg_fn_s* f);
 void release(sg_pred_s* p);
 bool is_elementwise(const sg_node_s* n);
+// computed by a step of its own: matrix product, quicksort, concatenation
+inline bool is_kernel_node(const sg_node_s* n) { return n->op >= OPN_MATMUL; }
 bool is_collection(const sg_node_s* n);
 void emit_fn(std::vector<sg::SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt);
 void emit_pred(std::vector<sg::SgOp>& prog, const sg_pred_s* p, int r, sg_dtype dt);
@@ -265,5 +269,11 @@ struct sg_mlp_s {
 
 namespace sgrt {
 sg_status build_plan(sg_program_s* P, Plan* out);
+// Run the step of a quicksort or concatenation node (host-driven; synchronizes the stream).
+// `results` are the execution's device results (a compacted source's count is read from the
+// pass that made it); `slot` is this step's result slot, which receives the output's count.
+sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, sg::InstResult* results, sg::InstResult* slot);
+// sort m items into out (quicksort of Listing 3); *count = items kept
+sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, bool is_f32, int64_t* count);
 sg_status execute_program(sg_program_s* P, sg_verdict* v, int32_t cap, int32_t* nv);
 }  // namespace sgrt
