@@ -24,6 +24,7 @@ from .elem import apply_fn, eval_pred
 from .reduce import exact_sum, exact_sum_f32, abs_sum, fmax_total, fmin_total, for_all, exists, is_sorted
 from .matrix import matmul64, product_check
 from .sort import quicksort
+from .linalg import transpose, matvec, quotient_holds
 
 STATUS = {"ok": 0, "pre_violated": 16, "post_violated": 17}
 MODES = ("off", "pre", "pre_post")
@@ -105,11 +106,39 @@ def _node_table(spec):
     return tab
 
 
+def builtin_contracts(spec: dict) -> list:
+    """Clauses a program gets from the library's own operations, ahead of its user clauses:
+    for each compwise_divide (zip "div") reachable from an output, taken in node order when its
+    output is added, require for_all(divisor /= 0) and ensure quotient (Listing 2)."""
+    by_name = {nd["name"]: nd for nd in spec["nodes"]}
+    order = {nd["name"]: k for k, nd in enumerate(spec["nodes"])}
+    out, seen = [], set()
+    for o in spec.get("outputs", []):
+        reach, stack = set(), [o]
+        while stack:
+            x = stack.pop()
+            if x in reach or x not in by_name:
+                continue
+            reach.add(x)
+            nd = by_name[x]
+            stack += [nd[k] for k in ("src", "a", "b", "m", "v") if k in nd]
+        for x in sorted(reach, key=order.get):
+            nd = by_name[x]
+            if nd["op"] == "zip" and nd["binop"] == "div" and x not in seen:
+                seen.add(x)
+                out.append({"kind": "require", "check": "for_all", "node": nd["b"], "pred": ["cmp", "ne", 0.0],
+                            "builtin": True})
+                out.append({"kind": "ensure", "check": "quotient", "node": x, "a": nd["a"], "b": nd["b"],
+                            "builtin": True})
+    return out
+
+
 def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
     if mode not in MODES:
         raise ValueError(mode)
     tab = _node_table(spec)
     vals = {}
+    aux = {}  # float64 values and error scales of matrix-vector products
     for inp in spec["inputs"]:
         a = np.asarray(inputs[inp["name"]])
         want = np.float32 if inp["dtype"] == "f32" else np.int32
@@ -133,8 +162,11 @@ def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
             if a["dtype"] == "f32":
                 x, y = va.astype(np.float64), vb.astype(np.float64)
                 with np.errstate(all="ignore"):
-                    r = {"add": x + y, "sub": x - y, "mul": x * y}[nd["binop"]]
+                    # + - x /: the float64 result rounded once is the correctly rounded binary32 one
+                    r = {"add": x + y, "sub": x - y, "mul": x * y, "div": x / y}[nd["binop"]]
                     v = r.astype(np.float32)
+            elif nd["binop"] == "div":
+                raise ShapeError("compwise_divide is defined on f32")
             else:
                 x, y = va.astype(np.int64), vb.astype(np.int64)
                 from .elem import wrap_i32
@@ -152,6 +184,26 @@ def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
             r = _reduce(nd["red"], vals[nd["src"]].reshape(-1), src["dtype"])
             tab[nd["name"]] = {"kind": "scalar", "dtype": r["dtype"], "shape": ()}
             vals[nd["name"]] = r
+        elif op == "transpose":
+            a = tab[nd["src"]]
+            if len(a["shape"]) != 2:
+                raise ShapeError("transpose needs a matrix")
+            v = transpose(vals[nd["src"]])
+            tab[nd["name"]] = {"kind": "coll", "dtype": a["dtype"], "shape": v.shape}
+            vals[nd["name"]] = v
+        elif op == "matvec":
+            m, x = tab[nd["m"]], tab[nd["v"]]
+            if len(m["shape"]) != 2 or m["dtype"] != "f32" or x["dtype"] != "f32":
+                raise ShapeError("a matrix-vector product needs an f32 matrix and an f32 vector")
+            r, c = m["shape"]
+            cnt = vals[nd["v"]].size
+            if cnt != (c if nd["side"] == "right" else r):
+                raise ShapeError("matrix-vector product: the vector's count does not match the matrix")
+            v32, v64, vabs = matvec(vals[nd["m"]], vals[nd["v"]], nd["side"])
+            shape = (r, 1) if nd["side"] == "right" else (1, c)
+            tab[nd["name"]] = {"kind": "coll", "dtype": "f32", "shape": shape}
+            vals[nd["name"]] = v32.reshape(shape)
+            aux[nd["name"]] = {"exact": v64, "abs": vabs}
         elif op == "concat":
             # Table 2 concatenate: the items of a followed by those of b
             a, b = tab[nd["a"]], tab[nd["b"]]
@@ -180,7 +232,8 @@ def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
             raise ValueError(op)
 
     res = OracleResult(status="ok")
-    contracts = spec.get("contracts", [])
+    res.aux = aux
+    contracts = builtin_contracts(spec) + list(spec.get("contracts", []))
     res.verdicts = [Verdict(-1, -1, 0.0) for _ in contracts]
 
     def check(c):
@@ -202,6 +255,10 @@ def evaluate(spec: dict, inputs: dict, mode: str = "pre_post") -> OracleResult:
             dev = abs(s["value"] - s["exact"])
             bound = c.get("abs_tol", 0.0) + c.get("rel_tol", 0.0) * asum
             return Verdict(int(dev <= bound), -1, dev)
+        if chk == "quotient":
+            ok = quotient_holds(vals[c["node"]].reshape(-1), vals[c["a"]].reshape(-1), vals[c["b"]].reshape(-1))
+            h, i = for_all(ok)
+            return Verdict(int(h), i, 0.0)
         if chk == "count_eq":
             # scalar contract Result.count = old a.count (Listing 3): the operands are never
             # changed by the body, so the old count is the count
