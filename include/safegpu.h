@@ -179,6 +179,15 @@ sg_status sg_concat(sg_node a, sg_node b, sg_node* out);
  * count can be smaller than the input's: attach sg_program_count_eq to check it.  Capacity =
  * the input's capacity. */
 sg_status sg_quicksort(sg_node in, sg_node* out);
+/* Determinant of a square f32 matrix by Gaussian elimination (Section 5, Listing 5, in its
+ * textbook form: partial pivoting, a zero pivot column means det = 0), in float64 on the
+ * widened input, as a scalar node.  Built-in precondition rows = columns (SG_E_SHAPE).  The
+ * elimination loop (3n + 1 kernels) is captured into a HIP graph once per node and replayed.
+ * sg_scalar_get gives f = the determinant as a double (+-inf beyond its range), i = its sign;
+ * sg_det_parts the exact representation. */
+sg_status sg_gauss_det(sg_node A, sg_node* out);
+/* det = sign * mant * 2^expo with mant in [0.5, 1) (0, 0.0, 0 when singular). */
+sg_status sg_det_parts(sg_node det, int32_t* sign, double* mant, int64_t* expo);
 sg_status sg_release(sg_node n);
 
 /* ---- programs: roots plus require/ensure clauses ---------------------------------------- */

@@ -86,7 +86,8 @@ def _sig(lib):
         "sg_pred_release": [H],
         "sg_map": [H, H, P(H)], "sg_zip": [H, H, c_int, P(H)], "sg_filter": [H, H, P(H)], "sg_reduce": [H, c_int, P(H)],
         "sg_matmul": [H, H, P(H)], "sg_release": [H], "sg_concat": [H, H, P(H)], "sg_quicksort": [H, P(H)],
-        "sg_item": [H, c_int64, P(c_double), P(c_int64)], "sg_program_count_eq": [H, c_int, H, H, P(c_int32)],
+        "sg_item": [H, c_int64, P(c_double), P(c_int64)], "sg_gauss_det": [H, P(H)],
+        "sg_det_parts": [H, P(c_int32), P(c_double), P(c_int64)], "sg_program_count_eq": [H, c_int, H, H, P(c_int32)],
         "sg_program_create": [H, P(H)], "sg_program_add_root": [H, H],
         "sg_program_quant": [H, c_int, c_int, H, H, P(c_int32)], "sg_program_sorted": [H, c_int, H, P(c_int32)],
         "sg_program_close": [H, c_int, H, c_double, c_double, P(c_int32)],
@@ -290,6 +291,16 @@ class Node:
     def quicksort(self):
         """The quicksort of the collection API (pivot at count // 2, three stable filters)."""
         return self._new(load().sg_quicksort, self.h)
+
+    def gauss_det(self):
+        """Determinant of this square matrix by Gaussian elimination (a scalar node)."""
+        return self._new(load().sg_gauss_det, self.h)
+
+    def det_parts(self):
+        """(sign, mantissa in [0.5, 1), binary exponent) of a determinant node."""
+        s, m, e = c_int32(), c_double(), c_int64()
+        _check(load().sg_det_parts(self.h, byref(s), byref(m), byref(e)), self.ctx.h)
+        return s.value, m.value, e.value
 
     def item(self, i: int):
         """The item at 0-based index i (float for f32 collections, int for i32)."""
@@ -671,6 +682,8 @@ def build_spec(ctx: Context, spec: dict, tensors: dict) -> Built:
             nodes[nd["name"]] = nodes[nd["a"]].concat(nodes[nd["b"]])
         elif op == "qsort":
             nodes[nd["name"]] = nodes[nd["src"]].quicksort()
+        elif op == "gauss_det":
+            nodes[nd["name"]] = nodes[nd["src"]].gauss_det()
         else:
             raise ValueError(op)
     prog = Program(ctx)

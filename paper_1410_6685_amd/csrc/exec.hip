@@ -408,7 +408,7 @@ sg_status launch_program(sg_program_s* P, ExecSlot& es) {
         } else if (step.kind == Step::NODE) {
             sg_node_s* nd = step.node;
             if ((st = alloc_output(ctx, nd)) != SG_OK) return st;
-            t_begin(nd->op == OPN_QSORT ? "quicksort" : "concat");
+            t_begin(node_step_name(nd));
             st = run_node_step(ctx, plan, nd, S.results, S.results + next_node++);
             t_end();
             if (st != SG_OK) return st;
@@ -718,7 +718,7 @@ static sg_status trigger(sg_node n) {
 
 sg_status sg_scalar_get(sg_node s, double* f, int64_t* i) {
     if (!s) return fail(nullptr, SG_E_INVALID, "scalar_get: NULL node");
-    if (s->op != OPN_REDUCE) return fail(s->ctx, SG_E_INVALID, "scalar_get: not a scalar node");
+    if (s->op != OPN_REDUCE && s->op != OPN_GAUSS) return fail(s->ctx, SG_E_INVALID, "scalar_get: not a scalar node");
     sg_status st = trigger(s);
     if (st != SG_OK) return st;
     if (f) *f = s->fval;

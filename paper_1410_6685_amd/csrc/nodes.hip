@@ -60,8 +60,10 @@ sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, InstResul
             SG_HIP(ctx, hipMemcpyAsync((char*)n->dev + (size_t)ca * 4, n->src[1]->dev, (size_t)cb * 4,
                                        hipMemcpyDeviceToDevice, ctx->stream));
         count = ca + cb;
+    } else if (n->op == OPN_GAUSS) {
+        return run_gauss(ctx, n);  // a scalar: no count
     } else {
-        return fail(ctx, SG_E_INVALID, "run_node_step: not a quicksort or concatenation");
+        return fail(ctx, SG_E_INVALID, "run_node_step: not a quicksort, concatenation or determinant");
     }
     n->count = count;
     hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(1), 0, ctx->stream, &slot->scan_count, count);
@@ -70,4 +72,19 @@ sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, InstResul
     return SG_OK;
 }
 
+const char* node_step_name(const sg_node_s* n) {
+    return n->op == OPN_QSORT ? "quicksort" : n->op == OPN_CONCAT ? "concat" : n->op == OPN_GAUSS ? "gauss" : "node";
+}
+
 }  // namespace sgrt
+
+extern "C" sg_status sg_det_parts(sg_node s, int32_t* sign, double* mant, int64_t* expo) {
+    if (!s) return sgrt::fail(nullptr, SG_E_INVALID, "det_parts: NULL node");
+    if (s->op != sgrt::OPN_GAUSS) return sgrt::fail(s->ctx, SG_E_INVALID, "det_parts: not a determinant node");
+    sg_status st = sg_scalar_get(s, nullptr, nullptr);  // executes the node if needed
+    if (st != SG_OK) return st;
+    if (sign) *sign = s->det_sign;
+    if (mant) *mant = s->det_mant;
+    if (expo) *expo = s->det_expo;
+    return SG_OK;
+}

@@ -193,6 +193,7 @@ void release(sg_pred_s* p) {
 void release(sg_node_s* n) {
     if (!n || --n->refs > 0) return;
     if (n->owned && n->dev) dev_free(n->ctx, n->dev);
+    if (n->op == OPN_GAUSS && n->aux) gauss_cache_free(n->ctx, n->aux);
     release(n->src[0]);
     release(n->src[1]);
     release(n->fn);
@@ -208,7 +209,7 @@ void release(sg_node_s* n) {
 bool is_elementwise(const sg_node_s* n) {
     return n->op == OPN_MAP || n->op == OPN_ZIP || n->op == OPN_FILTER || n->op == OPN_REDUCE;
 }
-bool is_collection(const sg_node_s* n) { return n->op != OPN_REDUCE; }
+bool is_collection(const sg_node_s* n) { return n->op != OPN_REDUCE && n->op != OPN_GAUSS; }
 
 // value dtype after applying fn to dtype
 bool fn_out_dtype(const sg_fn_s* f, sg_dtype in, sg_dtype* out, std::string* why) {
@@ -666,6 +667,20 @@ sg_status sg_quicksort(sg_node in, sg_node* out) {
     auto* nd = new_node(in->ctx, OPN_QSORT, in->dtype, in->n);
     nd->src[0] = in; retain(in);
     nd->space = nd->id;  // dropped items make the count device-side
+    *out = nd;
+    return SG_OK;
+}
+
+sg_status sg_gauss_det(sg_node A, sg_node* out) {
+    sg_ctx_s* ctx = A ? A->ctx : nullptr;
+    if (!A || !out) return fail(ctx, SG_E_INVALID, "gauss_det: NULL argument");
+    if (!A->matrix) return fail(ctx, SG_E_SHAPE, "gauss_det: operand must be a matrix");
+    if (A->rows != A->cols) return fail(ctx, SG_E_SHAPE, "gauss_det: the matrix must be square (rows = columns)");
+    if (A->dtype != SG_F32) return fail(ctx, SG_E_DTYPE, "gauss_det: f32 matrices (eliminated in float64)");
+    if (A->rows > 46340) return fail(ctx, SG_E_UNSUPPORTED, "gauss_det: at most 46340 rows");
+    auto* nd = new_node(ctx, OPN_GAUSS, SG_F64, 1);
+    nd->src[0] = A; retain(A);
+    nd->space = 0;
     *out = nd;
     return SG_OK;
 }

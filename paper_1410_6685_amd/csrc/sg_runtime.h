@@ -15,7 +15,7 @@
 namespace sgrt {
 
 // OPN_MATMUL and later: "kernel nodes", computed by a step of their own (not a streaming pass)
-enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL, OPN_QSORT, OPN_CONCAT };
+enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL, OPN_QSORT, OPN_CONCAT, OPN_GAUSS };
 enum NodeState { ST_NONE = 0, ST_COMPUTED = 1, ST_UNPUBLISHED = 2 };
 enum FnKind { FK_AFFINE = 0, FK_ADDC, FK_MULC, FK_UNARY, FK_COMPOSE };
 enum PredKind { PK_CMP = 0, PK_FINITE, PK_RANGE, PK_TRUE, PK_AND, PK_OR, PK_NOT };
@@ -108,6 +108,10 @@ struct sg_node_s {
     double f64 = 0.0;      // float64 shadow of float sums / averages
     int64_t ival = 0;      // integer scalar value
     const int64_t* count_dev = nullptr;  // device address of a compacted collection's count
+    void* aux = nullptr;   // kernel-node state kept between executions (determinant: workspace, graph)
+    int32_t det_sign = 0;  // determinant = det_sign * det_mant * 2^det_expo
+    double det_mant = 0.0;
+    int64_t det_expo = 0;
 };
 
 namespace sgrt {
@@ -275,5 +279,9 @@ sg_status build_plan(sg_program_s* P, Plan* out);
 sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, sg::InstResult* results, sg::InstResult* slot);
 // sort m items into out (quicksort of Listing 3); *count = items kept
 sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, bool is_f32, int64_t* count);
+// determinant by Gaussian elimination (graph-captured loop); sets the node's scalar fields
+sg_status run_gauss(sg_ctx_s* ctx, sg_node_s* node);
+void gauss_cache_free(sg_ctx_s* ctx, void* cache);
+const char* node_step_name(const sg_node_s* n);
 sg_status execute_program(sg_program_s* P, sg_verdict* v, int32_t cap, int32_t* nv);
 }  // namespace sgrt
