@@ -63,7 +63,7 @@ typedef enum sg_fn_kind {
 } sg_fn_kind;
 
 typedef enum sg_cmp { SG_LT = 0, SG_LE = 1, SG_GT = 2, SG_GE = 3, SG_EQ = 4, SG_NE = 5 } sg_cmp;
-typedef enum sg_binop { SG_ADD = 0, SG_SUB = 1, SG_MUL = 2 } sg_binop;
+typedef enum sg_binop { SG_ADD = 0, SG_SUB = 1, SG_MUL = 2, SG_DIV = 3 } sg_binop;
 typedef enum sg_red { SG_SUM = 0, SG_MIN = 1, SG_MAX = 2, SG_AVG = 3, SG_COUNT = 4 } sg_red;
 typedef enum sg_clause { SG_REQUIRE = 0, SG_ENSURE = 1 } sg_clause;
 typedef enum sg_quant { SG_FOR_ALL = 0, SG_EXISTS = 1 } sg_quant;
@@ -87,7 +87,7 @@ typedef struct sg_verdict {
 } sg_verdict;
 
 enum { SG_CHECK_FOR_ALL = 0, SG_CHECK_EXISTS = 1, SG_CHECK_SORTED = 2, SG_CHECK_CLOSE = 3,
-       SG_CHECK_PRODUCT = 4, SG_CHECK_COUNT_EQ = 5 };
+       SG_CHECK_PRODUCT = 4, SG_CHECK_COUNT_EQ = 5, SG_CHECK_QUOTIENT = 6 };
 
 /* ---- context ---------------------------------------------------------------------------- */
 
@@ -165,10 +165,27 @@ sg_status sg_pred_release(sg_pred p);
 /* ---- lazy operations ------------------------------------------------------------------- */
 
 sg_status sg_map(sg_node in, sg_fn f, sg_node* out);                      /* project */
-sg_status sg_zip(sg_node a, sg_node b, sg_binop op, sg_node* out);        /* plus/minus/compwise */
+/* Vector plus / minus / compwise multiply / compwise_divide (Section 3.3).  Built-in scalar
+ * contract: equal counts and dimensions, same index space (SG_E_SHAPE).  SG_DIV is defined on
+ * f32 and carries the built-in clauses of Listing 2, which a program receives when a root that
+ * depends on the division is added (in node creation order, after the clauses already there):
+ * require for_all(divisor /= 0) over the divisor and ensure quotient (SG_CHECK_QUOTIENT):
+ * RN(q * d) = n, or |RN(q * d) - n| <= 4u |n| + 2^-149 |d| with u = 2^-24, for every item
+ * (the float reading of Result * other = Current).  'Current = old Current' holds by
+ * construction: operations never change their operands. */
+sg_status sg_zip(sg_node a, sg_node b, sg_binop op, sg_node* out);
 sg_status sg_filter(sg_node in, sg_pred p, sg_node* out);                 /* stable */
 sg_status sg_reduce(sg_node in, sg_red red, sg_node* out);                /* scalar node */
 sg_status sg_matmul(sg_node A, sg_node B, sg_node* out);                  /* FP32 matrix cores */
+/* Matrix transposition (Section 3.4 transpose): rows x cols -> cols x rows, row-major. */
+sg_status sg_transpose(sg_node M, sg_node* out);
+/* Matrix-vector products (Section 3.4 right_multiply / left_multiply, Listing 1) of an f32
+ * matrix M (r x c) and a dense f32 vector v: side 0 (right) M v with count(v) = c -> r x 1;
+ * side 1 (left) v M with count(v) = r -> 1 x c (built-in scalar contracts, SG_E_SHAPE).  Each
+ * entry is a float64 sum of the exact float32 products in a fixed order, rounded to float32.
+ * A right product of a transposed matrix is planned as the left product of the original
+ * (the transpose is not materialized; the result keeps its c x 1 shape). */
+sg_status sg_matvec(sg_node M, sg_node v, int side, sg_node* out);
 /* concatenate (Table 2): the items of a followed by those of b (same element type; vectors).
  * Capacity a.capacity + b.capacity; count a.count + b.count. */
 sg_status sg_concat(sg_node a, sg_node b, sg_node* out);

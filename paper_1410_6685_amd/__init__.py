@@ -24,10 +24,10 @@ DTYPES = {"f32": F32, "i32": I32}
 MODES = {"off": 0, "pre": 1, "pre_post": 2}
 FN_UNARY = {"square": 1, "neg": 2, "abs": 3, "sqrt": 4, "sqrt_abs": 5, "exp": 6, "exp_neg_sq": 7, "i2f": 8}
 CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5}
-BINOP = {"add": 0, "sub": 1, "mul": 2}
+BINOP = {"add": 0, "sub": 1, "mul": 2, "div": 3}
 RED = {"sum": 0, "min": 1, "max": 2, "avg": 3, "count": 4}
 CLAUSE = {"require": 0, "ensure": 1}
-CHECKS = {0: "for_all", 1: "exists", 2: "sorted", 3: "close", 4: "product", 5: "count_eq"}
+CHECKS = {0: "for_all", 1: "exists", 2: "sorted", 3: "close", 4: "product", 5: "count_eq", 6: "quotient"}
 
 
 class Plan(ctypes.Structure):
@@ -87,6 +87,7 @@ def _sig(lib):
         "sg_map": [H, H, P(H)], "sg_zip": [H, H, c_int, P(H)], "sg_filter": [H, H, P(H)], "sg_reduce": [H, c_int, P(H)],
         "sg_matmul": [H, H, P(H)], "sg_release": [H], "sg_concat": [H, H, P(H)], "sg_quicksort": [H, P(H)],
         "sg_item": [H, c_int64, P(c_double), P(c_int64)], "sg_gauss_det": [H, P(H)],
+        "sg_transpose": [H, P(H)], "sg_matvec": [H, H, c_int, P(H)],
         "sg_det_parts": [H, P(c_int32), P(c_double), P(c_int64)], "sg_program_count_eq": [H, c_int, H, H, P(c_int32)],
         "sg_program_create": [H, P(H)], "sg_program_add_root": [H, H],
         "sg_program_quant": [H, c_int, c_int, H, H, P(c_int32)], "sg_program_sorted": [H, c_int, H, P(c_int32)],
@@ -291,6 +292,17 @@ class Node:
     def quicksort(self):
         """The quicksort of the collection API (pivot at count // 2, three stable filters)."""
         return self._new(load().sg_quicksort, self.h)
+
+    def transpose(self):
+        return self._new(load().sg_transpose, self.h)
+
+    def right_multiply(self, v: "Node"):
+        """M v (an r x 1 matrix)."""
+        return self._new(load().sg_matvec, self.h, v.h, 0)
+
+    def left_multiply(self, v: "Node"):
+        """v M (a 1 x c matrix)."""
+        return self._new(load().sg_matvec, self.h, v.h, 1)
 
     def gauss_det(self):
         """Determinant of this square matrix by Gaussian elimination (a scalar node)."""
@@ -682,6 +694,11 @@ def build_spec(ctx: Context, spec: dict, tensors: dict) -> Built:
             nodes[nd["name"]] = nodes[nd["a"]].concat(nodes[nd["b"]])
         elif op == "qsort":
             nodes[nd["name"]] = nodes[nd["src"]].quicksort()
+        elif op == "transpose":
+            nodes[nd["name"]] = nodes[nd["src"]].transpose()
+        elif op == "matvec":
+            m, v = nodes[nd["m"]], nodes[nd["v"]]
+            nodes[nd["name"]] = m.right_multiply(v) if nd["side"] == "right" else m.left_multiply(v)
         elif op == "gauss_det":
             nodes[nd["name"]] = nodes[nd["src"]].gauss_det()
         else:

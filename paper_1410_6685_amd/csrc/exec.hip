@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -540,6 +541,8 @@ static sg_status check_idle(sg_program p, const char* what) {
     return SG_OK;
 }
 
+static sg_status add_contract(sg_program p, sgrt::Contract c, int32_t* id);
+
 sg_status sg_program_add_root(sg_program p, sg_node n) {
     if (!p || !n) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "add_root: NULL argument");
     if (sg_status st = check_idle(p, "add_root")) return st;
@@ -547,6 +550,40 @@ sg_status sg_program_add_root(sg_program p, sg_node n) {
     retain(n);
     p->roots.push_back(n);
     p->plan.valid = false;
+    // built-in clauses of the operations the root depends on (Listing 2 for compwise_divide),
+    // in node creation order, once per operation
+    std::vector<sg_node_s*> divs, stack{n};
+    std::set<sg_node_s*> seen;
+    while (!stack.empty()) {
+        sg_node_s* x = stack.back();
+        stack.pop_back();
+        if (!x || !seen.insert(x).second) continue;
+        if (x->op == OPN_ZIP && x->binop == SG_DIV) divs.push_back(x);
+        stack.push_back(x->src[0]);
+        stack.push_back(x->src[1]);
+    }
+    std::sort(divs.begin(), divs.end(), [](sg_node_s* a, sg_node_s* b) { return a->id < b->id; });
+    for (sg_node_s* d : divs) {
+        if (std::find(p->builtin_done.begin(), p->builtin_done.end(), d) != p->builtin_done.end()) continue;
+        p->builtin_done.push_back(d);
+        sg_pred nz = nullptr;
+        if (sg_status st = sg_pred_cmp(SG_NE, 0.0, &nz)) return st;
+        sgrt::Contract r;
+        r.kind = SG_REQUIRE;
+        r.check = SG_CHECK_FOR_ALL;
+        r.node = d->src[1];
+        r.pred = nz;
+        sg_status st = add_contract(p, r, nullptr);
+        sg_pred_release(nz);  // the clause holds its own reference
+        if (st != SG_OK) return st;
+        sgrt::Contract q;
+        q.kind = SG_ENSURE;
+        q.check = SG_CHECK_QUOTIENT;
+        q.node = d;
+        q.a = d->src[0];
+        q.b = d->src[1];
+        if ((st = add_contract(p, q, nullptr)) != SG_OK) return st;
+    }
     return SG_OK;
 }
 

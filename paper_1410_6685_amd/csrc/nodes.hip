@@ -62,6 +62,8 @@ sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, InstResul
         count = ca + cb;
     } else if (n->op == OPN_GAUSS) {
         return run_gauss(ctx, n);  // a scalar: no count
+    } else if (n->op == OPN_TRANSPOSE || n->op == OPN_MATVEC) {
+        return run_linalg(ctx, n);  // dense: count = capacity
     } else {
         return fail(ctx, SG_E_INVALID, "run_node_step: not a quicksort, concatenation or determinant");
     }
@@ -73,7 +75,14 @@ sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, InstResul
 }
 
 const char* node_step_name(const sg_node_s* n) {
-    return n->op == OPN_QSORT ? "quicksort" : n->op == OPN_CONCAT ? "concat" : n->op == OPN_GAUSS ? "gauss" : "node";
+    switch (n->op) {
+        case OPN_QSORT: return "quicksort";
+        case OPN_CONCAT: return "concat";
+        case OPN_GAUSS: return "gauss";
+        case OPN_TRANSPOSE: return "transpose";
+        case OPN_MATVEC: return "matvec";
+        default: return "node";
+    }
 }
 
 }  // namespace sgrt

@@ -101,6 +101,14 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
         if (c.check == SG_CHECK_CLOSE && (c.node->op != OPN_REDUCE || c.node->red != SG_SUM || c.node->dtype != SG_F32))
             return fail(ctx, SG_E_INVALID, "close contract needs a float sum node");
     }
+    // a quotient check reads the division's operands with its result: when the result is read
+    // back from memory, so are they
+    for (int ci : plan->active) {
+        const Contract& c = P->contracts[ci];
+        if (c.check != SG_CHECK_QUOTIENT || !cut.count(c.node)) continue;
+        for (auto* x : {c.a, c.b})
+            if (is_elementwise(x)) { mat.insert(x); cut.insert(x); }
+    }
 
     // ---- passes ------------------------------------------------------------------------
     // Element-wise nodes joined by register operands form one pass each.  Passes that read a
@@ -144,6 +152,12 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
             if (c.check == SG_CHECK_CLOSE) { dsu.u(vnode[t], v); continue; }
             if (is_source_node(t, cut)) dsu.u(src_vertex(t, -1 - ci), v);
             else dsu.u(vnode[t], v);
+            if (c.check == SG_CHECK_QUOTIENT) {  // the operands are read in the same pass
+                for (auto* x : {c.a, c.b}) {
+                    if (is_source_node(x, cut)) dsu.u(src_vertex(x, -1 - ci), v);
+                    else dsu.u(vnode[x], v);
+                }
+            }
         }
         // group by component
         std::map<int, std::vector<sg_node_s*>> comp_nodes;
@@ -334,8 +348,16 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                     use(c.node->src[0], pos[c.node]);
                 } else if (in_pass.count(c.node)) {
                     use(c.node, pos[c.node]);
+                    if (c.check == SG_CHECK_QUOTIENT) {  // operands live past the division
+                        use(c.a, pos[c.node] + 1);
+                        use(c.b, pos[c.node] + 1);
+                    }
                 } else {
                     use(c.node, -1);
+                    if (c.check == SG_CHECK_QUOTIENT) {
+                        use(c.a, -1);
+                        use(c.b, -1);
+                    }
                 }
             }
             const int END = 1 << 30;
@@ -380,6 +402,15 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                     o.code = dt == SG_F32 ? CHK_SORTED_F : CHK_SORTED_I;
                     o.a = (uint8_t)r;
                     o.b = (uint8_t)r;  // sources sit in the register of their input index
+                } else if (c.check == SG_CHECK_QUOTIENT) {
+                    SgOp q{};
+                    q.code = P_QUOT;
+                    q.a = (uint8_t)r;
+                    q.b = (uint8_t)reg_of(c.a);
+                    q.dst = (uint8_t)reg_of(c.b);
+                    prog.push_back(q);
+                    o.code = CHK_ALL;
+                    o.sp = (uint8_t)space;
                 } else {
                     emit_pred(prog, c.pred, r, dt);
                     o.code = c.check == SG_CHECK_FOR_ALL ? CHK_ALL : CHK_ANY;
@@ -423,7 +454,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                     } break;
                     case OPN_ZIP: {
                         int ra = reg_of(n->src[0]), rb = reg_of(n->src[1]);
-                        const bool comm = n->binop != SG_SUB;
+                        const bool comm = n->binop == SG_ADD || n->binop == SG_MUL;
                         auto dies = [&](int r) {
                             return owner_last[r] <= i && !(owner[r] && mat.count(owner[r]) && sp[owner[r]] != 0);
                         };
@@ -446,7 +477,10 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                         reg[n] = rd;
                         SgOp o{};
                         const bool f = n->dtype == SG_F32;
-                        o.code = n->binop == SG_ADD ? (f ? F_ADD : I_ADD) : n->binop == SG_SUB ? (f ? F_SUB : I_SUB) : (f ? F_MUL : I_MUL);
+                        o.code = n->binop == SG_ADD   ? (f ? F_ADD : I_ADD)
+                                 : n->binop == SG_SUB ? (f ? F_SUB : I_SUB)
+                                 : n->binop == SG_MUL ? (f ? F_MUL : I_MUL)
+                                                      : F_DIV;
                         o.a = (uint8_t)ra;
                         o.b = (uint8_t)rb;
                         o.dst = (uint8_t)ra;

@@ -584,9 +584,10 @@ sg_status sg_map(sg_node in, sg_fn f, sg_node* out) {
 sg_status sg_zip(sg_node a, sg_node b, sg_binop op, sg_node* out) {
     sg_ctx_s* ctx = a ? a->ctx : (b ? b->ctx : nullptr);
     if (!a || !b || !out) return fail(ctx, SG_E_INVALID, "zip: NULL argument");
-    if (op < SG_ADD || op > SG_MUL) return fail(ctx, SG_E_INVALID, "zip: unknown operator");
+    if (op < SG_ADD || op > SG_DIV) return fail(ctx, SG_E_INVALID, "zip: unknown operator");
     if (!is_collection(a) || !is_collection(b)) return fail(ctx, SG_E_INVALID, "zip: operand is a scalar");
     if (a->dtype != b->dtype) return fail(ctx, SG_E_DTYPE, "zip: operands differ in element type");
+    if (op == SG_DIV && a->dtype != SG_F32) return fail(ctx, SG_E_DTYPE, "zip: compwise_divide is defined on f32");
     // built-in scalar contracts of vector arithmetic: equal counts (and equal dimensions)
     if (a->n != b->n) return fail(ctx, SG_E_SHAPE, "zip: operand counts differ");
     if (a->matrix && b->matrix && (a->rows != b->rows || a->cols != b->cols))
@@ -667,6 +668,49 @@ sg_status sg_quicksort(sg_node in, sg_node* out) {
     auto* nd = new_node(in->ctx, OPN_QSORT, in->dtype, in->n);
     nd->src[0] = in; retain(in);
     nd->space = nd->id;  // dropped items make the count device-side
+    *out = nd;
+    return SG_OK;
+}
+
+sg_status sg_transpose(sg_node M, sg_node* out) {
+    sg_ctx_s* ctx = M ? M->ctx : nullptr;
+    if (!M || !out) return fail(ctx, SG_E_INVALID, "transpose: NULL argument");
+    if (!M->matrix) return fail(ctx, SG_E_SHAPE, "transpose: operand must be a matrix");
+    if (M->space != 0) return fail(ctx, SG_E_SHAPE, "transpose: operand has no fixed shape (filtered)");
+    auto* nd = new_node(ctx, OPN_TRANSPOSE, M->dtype, M->n);
+    nd->src[0] = M; retain(M);
+    nd->matrix = true; nd->rows = M->cols; nd->cols = M->rows;
+    nd->space = 0;
+    *out = nd;
+    return SG_OK;
+}
+
+sg_status sg_matvec(sg_node M, sg_node v, int side, sg_node* out) {
+    sg_ctx_s* ctx = M ? M->ctx : nullptr;
+    if (!M || !v || !out) return fail(ctx, SG_E_INVALID, "matvec: NULL argument");
+    if (side != 0 && side != 1) return fail(ctx, SG_E_INVALID, "matvec: side is 0 (right) or 1 (left)");
+    if (!M->matrix) return fail(ctx, SG_E_SHAPE, "matvec: first operand must be a matrix");
+    if (!is_collection(v) || v->space != 0) return fail(ctx, SG_E_SHAPE, "matvec: the vector must be a dense collection");
+    if (M->dtype != SG_F32 || v->dtype != SG_F32) return fail(ctx, SG_E_DTYPE, "matvec: f32 operands");
+    const int64_t need = side == 0 ? M->cols : M->rows;
+    if (v->n != need)
+        return fail(ctx, SG_E_SHAPE, side == 0 ? "right_multiply: count(v) must equal the matrix's columns"
+                                               : "left_multiply: count(v) must equal the matrix's rows");
+    auto* nd = new_node(ctx, OPN_MATVEC, SG_F32, side == 0 ? M->rows : M->cols);
+    nd->matrix = true;
+    nd->rows = side == 0 ? M->rows : 1;
+    nd->cols = side == 0 ? 1 : M->cols;
+    nd->space = 0;
+    // M^T v = v M: read the transpose's operand in the other orientation
+    sg_node_s* src = M;
+    int s = side;
+    if (M->op == OPN_TRANSPOSE) {
+        src = M->src[0];
+        s = 1 - side;
+    }
+    nd->src[0] = src; retain(src);
+    nd->src[1] = v; retain(v);
+    nd->binop = s;  // side of the product as computed
     *out = nd;
     return SG_OK;
 }

@@ -46,11 +46,14 @@ enum OpCode : uint8_t {
     MOV,  // register dst = register a
     // value ops work in place: register a = f(a), or a = a (op) b
     F_AFFINE, F_ADDC, F_MULC, F_SQUARE, F_NEG, F_ABS, F_SQRT, F_SQRT_ABS, F_EXP, F_EXP_NEG_SQ,
-    F_ADD, F_SUB, F_MUL,
+    F_ADD, F_SUB, F_MUL, F_DIV,
     // i32 value ops (wrap modulo 2^32)
     I_AFFINE, I_ADDC, I_MULC, I_SQUARE, I_NEG, I_ABS, I_ADD, I_SUB, I_MUL, I_TO_F,
     // predicates push one bit per element onto a 4-deep stack
-    P_TRUE, P_CMP_F, P_CMP_I, P_FINITE, P_RANGE_F, P_RANGE_I, P_AND, P_OR, P_NOT,
+    P_TRUE, P_CMP_F, P_CMP_I, P_FINITE, P_RANGE_F, P_RANGE_I,
+    // quotient check of a division: registers a = RN(n / d), b = n, dst = d
+    P_QUOT,
+    P_AND, P_OR, P_NOT,
     // FILTER pops: space[sp] = space[sp2] & top
     FILTER,
     // CHK_ALL / CHK_ANY pop: first element of space sp where top is false / true -> slot aux

@@ -15,7 +15,8 @@
 namespace sgrt {
 
 // OPN_MATMUL and later: "kernel nodes", computed by a step of their own (not a streaming pass)
-enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL, OPN_QSORT, OPN_CONCAT, OPN_GAUSS };
+enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL, OPN_QSORT, OPN_CONCAT, OPN_GAUSS,
+              OPN_TRANSPOSE, OPN_MATVEC };
 enum NodeState { ST_NONE = 0, ST_COMPUTED = 1, ST_UNPUBLISHED = 2 };
 enum FnKind { FK_AFFINE = 0, FK_ADDC, FK_MULC, FK_UNARY, FK_COMPOSE };
 enum PredKind { PK_CMP = 0, PK_FINITE, PK_RANGE, PK_TRUE, PK_AND, PK_OR, PK_NOT };
@@ -242,6 +243,7 @@ struct sg_program_s {
     std::vector<sg_node_s*> roots;
     std::vector<sgrt::Contract> contracts;
     std::vector<sg_node_s*> splits;
+    std::vector<sg_node_s*> builtin_done;  // operations whose built-in clauses are attached
     // launch plan chosen for this program (autotuner / selector); 0 = the context default
     int block = 0, unroll = 0, substeps = 0;
     sg_node_s* plan_split = nullptr;  // extra fusion split point of the plan
@@ -281,6 +283,8 @@ sg_status run_node_step(sg_ctx_s* ctx, const Plan& plan, sg_node_s* n, sg::InstR
 sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, bool is_f32, int64_t* count);
 // determinant by Gaussian elimination (graph-captured loop); sets the node's scalar fields
 sg_status run_gauss(sg_ctx_s* ctx, sg_node_s* node);
+// transposition and matrix-vector products (linalg.hip)
+sg_status run_linalg(sg_ctx_s* ctx, sg_node_s* node);
 void gauss_cache_free(sg_ctx_s* ctx, void* cache);
 const char* node_step_name(const sg_node_s* n);
 sg_status execute_program(sg_program_s* P, sg_verdict* v, int32_t cap, int32_t* nv);
