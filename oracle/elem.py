@@ -109,6 +109,11 @@ def apply_fn(fn, x: np.ndarray, dtype: str):
     if name == "compose":
         v, d = apply_fn(fn[1], x, dtype)
         return apply_fn(fn[2], v, d)
+    if name == "expr":
+        if dtype != "f32":
+            raise ValueError("expression functions are defined on f32")
+        from .expr import apply_expr
+        return apply_expr(fn[1], x), "f32"
     if dtype == "f32":
         xf = _f64(x)
         with np.errstate(all="ignore"):
