@@ -305,10 +305,10 @@ def run_cfg5(ctx, n_train: int, n_test: int, seed: int = 51) -> dict:
     for i, p, msg in rejected[:3]:
         log(f"cfg5: plan {p} refused for chain {i} ({msg}): {json.dumps(train_specs[i])}")
     t_collect = time.perf_counter() - t0
-    X, y = tr.flat()
-    log(f"cfg5: training the cost model on {len(y)} samples")
+    n_samples = int(sum(len(m) for m in tr.ms))
+    log(f"cfg5: training the cost model on {n_samples} samples")
     t0 = time.perf_counter()
-    net, norm, losses = selector.train(ctx, tr, W.mlp_init_params(seed), epochs=60)
+    net, losses = selector.train(ctx, tr, W.mlp_init_params(seed), epochs=60)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del train_b
@@ -321,12 +321,14 @@ def run_cfg5(ctx, n_train: int, n_test: int, seed: int = 51) -> dict:
     for b, plans in zip(test_b[:200], te.plans[:200]):
         net.select(b.program, plans, 0.01)
     t_infer = (time.perf_counter() - t0) / min(200, len(test_b))
-    Xt, yt = te.flat()
-    pred = net.predict(torch.from_numpy(norm.apply(Xt)).cuda()).cpu().numpy()
-    return {"train_chains": n_train, "train_samples": int(len(y)), "test_chains": n_test,
-            "test_samples": int(len(yt)), "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
+    Xt, mst = te.device()
+    Xtn, yt = net.standardize(Xt, mst)
+    pred = net.predict(Xtn)
+    test_mse = float(((pred - yt) ** 2).mean().item())
+    return {"train_chains": n_train, "train_samples": n_samples, "test_chains": n_test,
+            "test_samples": int(yt.numel()), "collect_s": round(t_collect, 2), "train_s": round(t_train, 2),
             "final_train_mse_log_us": round(float(losses[-1]), 5),
-            "test_mse_log_us": round(float(np.mean((pred - yt) ** 2)), 5),
+            "test_mse_log_us": round(test_mse, 5),
             "fallback_rate": round(ev.fallback_rate, 4), "regret_geomean_pct": round(100 * ev.regret_geomean, 3),
             "regret_p90_pct": round(100 * ev.regret_p90, 3),
             "regret_learned_only_geomean_pct": round(100 * ev.regret_learned_only, 3),
@@ -350,8 +352,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 256 MiB device copy (profiling aid)")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the matrix-product workload")
     ap.add_argument("--cfg4-instances", type=int, default=10_000, help="0 skips the batched workload")
-    ap.add_argument("--cfg5-train", type=int, default=1500, help="training chains (0 skips the selector)")
-    ap.add_argument("--cfg5-test", type=int, default=500)
+    ap.add_argument("--cfg5-train", type=int, default=4200,
+                    help="training chains, about 12 candidate plans each: ~50k timings (0 skips the selector)")
+    ap.add_argument("--cfg5-test", type=int, default=5000, help="held-out chains")
     ap.add_argument("--interp", action="store_true", help="precompiled interpreter kernel instead of kernels "
                     "compiled for the program")
     args = ap.parse_args()

@@ -91,16 +91,23 @@ enum { SG_CHECK_FOR_ALL = 0, SG_CHECK_EXISTS = 1, SG_CHECK_SORTED = 2, SG_CHECK_
 
 /* ---- context ---------------------------------------------------------------------------- */
 
-/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the null
- * stream) on which all work is enqueued.  Mode defaults to SG_MODE_PRE_POST, fusion on. */
+/* Create a context on HIP device `device` (Section 2.2: the runtime that owns device memory
+ * and launches generated kernels); `hip_stream` is a hipStream_t (NULL = the null stream) on
+ * which all work is enqueued.  Mode defaults to SG_MODE_PRE_POST, fusion on.  SG_E_INVALID
+ * for a bad device or NULL out. */
 sg_status sg_ctx_create(int device, void* hip_stream, sg_ctx* out);
+/* Releases the context once every node, program and batch made from it is released. */
 sg_status sg_ctx_destroy(sg_ctx ctx);
+/* Contract monitoring mode (Section 6.3: no checking, preconditions only, pre- and
+ * postconditions).  SG_E_INVALID for an unknown mode. */
 sg_status sg_ctx_set_mode(sg_ctx ctx, sg_mode mode);
-/* fused != 0: fuse (default).  fused == 0: the naive plan of Section 5, one kernel per
- * operation and per contract, every intermediate materialized. */
+/* fused != 0: fuse (default; Section 5, Figures 2 and 3 after optimization).  fused == 0:
+ * the plan before optimization, one kernel per operation and per contract, every
+ * intermediate materialized. */
 sg_status sg_ctx_set_fusion(sg_ctx ctx, int fused);
-/* Launch plan for the streaming kernel: block size (64..1024, multiple of 64) and unroll
- * (1, 2 or 4: 16-byte loads per lane per input and sub-tile).  0 keeps the default. */
+/* Launch plan for the streaming kernel (the launch configuration of a generated kernel,
+ * Section 5): block size (64..1024, multiple of 64) and unroll (1, 2 or 4: 16-byte loads per
+ * lane per input and sub-tile).  0 keeps the default; other values give SG_E_INVALID. */
 sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll);
 /* on != 0: run every single-program pass through a kernel compiled at run time (hiprtc) for
  * that pass's program, as the paper generates one kernel per merged plan (Section 5);
@@ -109,7 +116,8 @@ sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll);
  * reported as SG_E_DEVICE with the compiler log in sg_last_error.  Batches always use the
  * interpreter. */
 sg_status sg_ctx_set_specialize(sg_ctx ctx, int on);
-/* Record the device time of every kernel launch with HIP events on the context stream. */
+/* Record the device time of every kernel launch with HIP events on the context stream (the
+ * measurements of Section 6.1 without the host-side floor). */
 sg_status sg_ctx_set_timing(sg_ctx ctx, int on);
 /* Spin limit of the kernels' bounded waits (compaction prefixes, result finalization): a
  * wait that reaches it gives up, and the execution returns SG_E_DEVICE with the context's
@@ -133,26 +141,36 @@ const char* sg_last_error(sg_ctx ctx);
 
 /* ---- collections (Section 3.2 from_array; Section 3.4 row-major matrices) ------------- */
 
-/* Borrow `n` elements of device memory at `dev` (16-byte alignment gives 128-bit loads).
- * The caller keeps the memory alive and unmodified while any execution reads it. */
+/* Borrow `n` elements of device memory at `dev` (a collection of count = capacity = n,
+ * Section 3.2; 16-byte alignment gives 128-bit loads).  The caller keeps the memory alive
+ * and unmodified while any execution reads it.  SG_E_INVALID for a NULL address with n > 0
+ * or memory the HIP runtime does not know as device memory of the context's device. */
 sg_status sg_vector_wrap(sg_ctx ctx, sg_dtype dtype, void* dev, int64_t n, sg_node* out);
+/* A rows x cols matrix stored row-wise in one array (Section 3.4). */
 sg_status sg_matrix_wrap(sg_ctx ctx, sg_dtype dtype, void* dev, int64_t rows, int64_t cols, sg_node* out);
-/* Copy `n` host elements to new device memory owned by the node (from_array). */
+/* from_array (Table 2): copy `n` host elements to new device memory owned by the node, in
+ * one copy (Section 3.2).  SG_E_OOM when the device memory cannot be had. */
 sg_status sg_vector_from_host(sg_ctx ctx, sg_dtype dtype, const void* host, int64_t n, sg_node* out);
 sg_status sg_matrix_from_host(sg_ctx ctx, sg_dtype dtype, const void* host, int64_t rows, int64_t cols, sg_node* out);
 
 /* ---- agents ---------------------------------------------------------------------------- */
 
-/* f32: x -> RN(RN(a*x) + b).  i32: x -> a*x + b modulo 2^32 (a, b truncated to int32). */
+/* Agents of type FUNCTION (Section 3.2, project): side-effect free element functions.
+ * f32: x -> RN(RN(a*x) + b).  i32: x -> a*x + b modulo 2^32 (a, b truncated to int32).
+ * Constants are rounded to the element type when the function is applied. */
 sg_status sg_fn_affine(double a, double b, sg_fn* out);
+/* x + c and x * c (the scalar operations of Section 3.3 with the vector's own rounding). */
 sg_status sg_fn_add_c(double c, sg_fn* out);
 sg_status sg_fn_mul_c(double c, sg_fn* out);
+/* One of sg_fn_kind (sqrt as in the project example of Section 3.2; exp correctly rounded).
+ * SG_E_INVALID for an unknown kind. */
 sg_status sg_fn_unary(sg_fn_kind kind, sg_fn* out);
-/* first f, then g */
+/* first f, then g (one agent made of two, evaluated as one expression, Figure 3) */
 sg_status sg_fn_compose(sg_fn f, sg_fn g, sg_fn* out);
 sg_status sg_fn_release(sg_fn f);
 
-/* Comparisons are IEEE comparisons against c rounded to the operand's element type. */
+/* Agents of type PREDICATE (Section 3.2, filter / for_all / exists).  Comparisons are IEEE
+ * comparisons against c rounded to the operand's element type (false with NaN). */
 sg_status sg_pred_cmp(sg_cmp op, double c, sg_pred* out);
 sg_status sg_pred_isfinite(sg_pred* out);
 sg_status sg_pred_in_range(double lo, double hi, sg_pred* out); /* lo <= x <= hi */
@@ -164,7 +182,9 @@ sg_status sg_pred_release(sg_pred p);
 
 /* ---- lazy operations ------------------------------------------------------------------- */
 
-sg_status sg_map(sg_node in, sg_fn f, sg_node* out);                      /* project */
+/* project (Table 2): a new collection of count(in) items, item i = f(in[i]).  Lazy: nothing
+ * runs until a trigger (Section 5).  SG_E_DTYPE when f is not defined on the element type. */
+sg_status sg_map(sg_node in, sg_fn f, sg_node* out);
 /* Vector plus / minus / compwise multiply / compwise_divide (Section 3.3).  Built-in scalar
  * contract: equal counts and dimensions, same index space (SG_E_SHAPE).  SG_DIV is defined on
  * f32 and carries the built-in clauses of Listing 2, which a program receives when a root that
@@ -174,9 +194,16 @@ sg_status sg_map(sg_node in, sg_fn f, sg_node* out);                      /* pro
  * (the float reading of Result * other = Current).  'Current = old Current' holds by
  * construction: operations never change their operands. */
 sg_status sg_zip(sg_node a, sg_node b, sg_binop op, sg_node* out);
-sg_status sg_filter(sg_node in, sg_pred p, sg_node* out);                 /* stable */
-sg_status sg_reduce(sg_node in, sg_red red, sg_node* out);                /* scalar node */
-sg_status sg_matmul(sg_node A, sg_node B, sg_node* out);                  /* FP32 matrix cores */
+/* filter (Table 2): the items of `in` for which p holds, in their order (stable); capacity
+ * = capacity(in), count known on the device after execution (Section 3.2). */
+sg_status sg_filter(sg_node in, sg_pred p, sg_node* out);
+/* sum / min / max / avg (Section 3.3, device-side reductions) and count (Table 2) as a
+ * scalar node.  Float sums accumulate in float64 in a fixed order; min / max of an empty
+ * collection are -inf / +inf (INT_MIN / INT_MAX), avg of an empty collection is NaN. */
+sg_status sg_reduce(sg_node in, sg_red red, sg_node* out);
+/* multiply (Section 3.4): C = A B for f32 matrices with cols(A) = rows(B) (built-in scalar
+ * contract, SG_E_SHAPE), on the FP32 matrix cores with FP32 accumulation. */
+sg_status sg_matmul(sg_node A, sg_node B, sg_node* out);
 /* Matrix transposition (Section 3.4 transpose): rows x cols -> cols x rows, row-major. */
 sg_status sg_transpose(sg_node M, sg_node* out);
 /* Matrix-vector products (Section 3.4 right_multiply / left_multiply, Listing 1) of an f32
@@ -209,26 +236,39 @@ sg_status sg_release(sg_node n);
 
 /* ---- programs: roots plus require/ensure clauses ---------------------------------------- */
 
+/* A program is the routine of Section 4: roots (the body) plus require and ensure clauses
+ * built from range queries, monitored per the context's mode. */
 sg_status sg_program_create(sg_ctx ctx, sg_program* out);
 sg_status sg_program_add_root(sg_program p, sg_node n);
-/* for_all / exists of predicate `pred` over collection `n`. */
+/* for_all / exists (Table 2) of predicate `pred` over collection `n` as a require or ensure
+ * clause (Section 4; the range preconditions of Listing 2).  The verdict's first_index is the
+ * first violating (for_all) or witnessing (exists) index; an empty collection satisfies
+ * for_all and fails exists, index -1.  *id receives the clause id. */
 sg_status sg_program_quant(sg_program p, sg_clause kind, sg_quant q, sg_node n, sg_pred pred, int32_t* id);
-/* non-decreasing order of collection `n`. */
+/* is_sorted (Section 3.3; the postcondition of Listing 3): non-decreasing order of
+ * collection `n`; first_index = the left item of the first pair out of order (a NaN breaks
+ * its pairs). */
 sg_status sg_program_sorted(sg_program p, sg_clause kind, sg_node n, int32_t* id);
-/* |value(s) - shadow(s)| <= abs_tol + rel_tol * sum|x| for a float sum node s, where the
+/* A sum postcondition (the scalar contracts of Section 6.3) made robust to rounding:
+ * |value(s) - shadow(s)| <= abs_tol + rel_tol * sum|x| for a float sum node s, where the
  * shadow is the same sum accumulated in float64 in the same pass. */
 sg_status sg_program_close(sg_program p, sg_clause kind, sg_node s, double abs_tol, double rel_tol, int32_t* id);
-/* Product check of C = A B with the nvec x N matrix R of probe vectors (one per row):
- * |C r - A(B r)|_i <= (gamma_2K + 2^-40) (|A|(|B||r|))_i for every probe and row. */
+/* Product check of C = A B (the product postcondition Result * other = Current of Listing 2,
+ * read with a rounding bound) with the nvec x N matrix R of probe vectors (one per row):
+ * |C r - A(B r)|_i <= (gamma_2K + 2^-40) (|A|(|B||r|))_i for every probe and row, in float64;
+ * first_index = the first violating row of the first violating probe. */
 sg_status sg_program_product(sg_program p, sg_clause kind, sg_node C, sg_node A, sg_node B, sg_node R, int32_t* id);
 /* Scalar contract count(n) = old count(other) (the postcondition Result.count = a.count of
  * Listing 3).  The operands are never changed by a program, so the old count is the count
  * before or after the body alike.  Evaluated after the body; measure = count(n) - count(other). */
 sg_status sg_program_count_eq(sg_program p, sg_clause kind, sg_node n, sg_node other, int32_t* id);
-/* Mark `n` as a fusion split point: it is materialized and its consumers start a new pass. */
+/* Mark `n` as a fusion split point of the execution plan (Section 5): it is materialized and
+ * its consumers start a new pass. */
 sg_status sg_program_split(sg_program p, sg_node n);
-/* Run the program (trigger "update").  Writes up to `cap` verdicts.  Returns SG_OK,
- * SG_PRE_VIOLATED (outputs unpublished) or SG_POST_VIOLATED, or an error code. */
+/* Run the program (the trigger update of Table 2; Section 5): plan, fuse, launch, then the
+ * contract protocol of Section 4 (a failed require means the body's results are not
+ * published).  Writes up to `cap` verdicts in clause order.  Returns SG_OK, SG_PRE_VIOLATED
+ * (outputs unpublished) or SG_POST_VIOLATED, or an error code. */
 sg_status sg_program_execute(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts);
 /* Asynchronous form of sg_program_execute, for loops that run a program repeatedly: launch
  * enqueues one execution on the context's stream and returns once it is enqueued; wait blocks
@@ -243,22 +283,26 @@ sg_status sg_program_launch(sg_program p);
 sg_status sg_program_wait(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts);
 sg_status sg_program_release(sg_program p);
 
-/* Execute roots without contracts (shorthand for a temporary program). */
+/* update (Table 2) of roots without contracts (shorthand for a temporary program). */
 sg_status sg_execute(sg_ctx ctx, const sg_node* roots, int32_t nroots);
 
 /* ---- triggers and results (Section 5: scalar query, to_array) --------------------------- */
 
-/* Scalar node value: f = value as double (a float sum is rounded to binary32 first),
- * i = integer value (counts, int sums, int min/max).  Executes the node if needed. */
+/* Scalar query (the trigger of Section 5 that returns a value, e.g. sum in Listing 4):
+ * f = value as double (a float sum is rounded to binary32 first), i = integer value (counts,
+ * int sums, int min/max).  Executes the node if needed.  SG_E_STATE when the value is
+ * unpublished (a failed require). */
 sg_status sg_scalar_get(sg_node s, double* f, int64_t* i);
 /* float64 shadow of a float sum or avg node (accumulated in float64 in the same pass). */
 sg_status sg_scalar_shadow(sg_node s, double* f64);
+/* count (Table 2) of a computed collection. */
 sg_status sg_count(sg_node c, int64_t* n);
 /* item (Table 2): the item at 0-based index i (executes the collection if needed); f = its
  * value as double, iv = as integer (i32 collections).  Built-in precondition 0 <= i < count,
  * else SG_E_INVALID. */
 sg_status sg_item(sg_node c, int64_t i, double* f, int64_t* iv);
-/* Copy a collection to host memory (at most cap elements); *n = its count. */
+/* Copy a collection to host memory in one copy (new_cursor of Table 2; Section 3.2), at most
+ * cap elements; *n = its count. */
 sg_status sg_to_host(sg_node c, void* dst, int64_t cap, int64_t* n);
 /* Device address and count of a computed collection (valid until the node is released or
  * recomputed). */
@@ -266,9 +310,10 @@ sg_status sg_device_ptr(sg_node c, void** dev, int64_t* n);
 
 /* ---- batched execution: many programs in one persistent launch -------------------------- */
 
-/* Plan `n` programs (each a chain with its own contracts) into one launch of the streaming
- * kernel; programs must contain no matrix product.  The plan and its launch are captured
- * into a HIP graph when use_graph != 0. */
+/* Plan `n` programs (each a chain with its own contracts, Section 4) into one launch of the
+ * streaming kernel; programs must contain no matrix product, sort or determinant
+ * (SG_E_UNSUPPORTED).  The plan and its launch are captured into a HIP graph when
+ * use_graph != 0 (the host-loop launch overhead of Section 6.1 paid once). */
 sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int use_graph, sg_batch* out);
 /* Launch once (graph replay or direct launch); results are published to the programs' roots
  * and verdicts. status_out[n] receives each program's status, verdicts are written program
@@ -299,7 +344,8 @@ sg_status sg_program_set_plan(sg_program p, const sg_plan* plan);
  *  16 log2 block, 17 log2 unroll, 18 log2 sub-steps, 19 has split, 20 split position,
  *  21 passes, 22 bytes moved per element, 23 resident blocks per CU. */
 sg_status sg_program_features(sg_program p, const sg_plan* plan, float* f24);
-/* Autotuner: device time in ms (median of reps runs after one warm-up) of every plan. */
+/* Autotuner of the optimizer's launch plans (Section 5's plan choice, measured): device time
+ * in ms (median of reps runs after one warm-up) of every plan. */
 sg_status sg_program_time_plans(sg_program p, const sg_plan* plans, int32_t n, int32_t reps, double* ms_out);
 /* Time every plan, set the fastest on the program; *best its index, ms_out (n) the timings. */
 sg_status sg_autotune(sg_program p, const sg_plan* plans, int32_t n, int32_t reps, int32_t* best, double* ms_out);
@@ -322,12 +368,57 @@ sg_status sg_mlp_train(sg_mlp m, const float* X_dev, const float* T_dev, int64_t
 sg_status sg_mlp_predict(sg_mlp m, const float* X_dev, int64_t n, float* Y_dev);
 /* Standardization x' = (x - mean) / scale and the training range [lo, hi] of each feature. */
 sg_status sg_mlp_set_norm(sg_mlp m, const float* mean24, const float* scale24, const float* lo24, const float* hi24);
+/* The model's standardization (SG_E_STATE if none is set). */
+sg_status sg_mlp_get_norm(sg_mlp m, float* mean24, float* scale24, float* lo24, float* hi24);
 /* Learned selector: predict all candidates, set the argmin on the program unless a feature
  * is out of the training range or the best two predictions are closer than `margin` (log
  * units), in which case *fallback = 1 and the program's plan is unchanged (the caller runs
  * the autotuner).  pred_out (n, optional) receives the predictions. */
 sg_status sg_select_plan(sg_mlp m, sg_program p, const sg_plan* plans, int32_t n, float margin, int32_t* best,
                          float* pred_out, int32_t* fallback);
+
+/* Training data of the cost model, prepared on the device: fits the model's standardization
+ * (per feature: float64 mean and population standard deviation, scale = 1 where it is below
+ * 1e-6, minimum and maximum) on the raw features X (n x 24, device), writes the standardized
+ * features Xn = (X - mean) / scale (float32 operations; device, n x 24) and, when ms_dev (n
+ * device doubles, measured milliseconds) is given, the targets T = RN32(log(1000 ms)) (device,
+ * n floats).  SG_E_INVALID for n < 1 or buffers outside device allocations. */
+sg_status sg_mlp_fit_data(sg_mlp m, const float* X_dev, const double* ms_dev, int64_t n, float* Xn_dev, float* T_dev);
+/* Xn = (X - mean) / scale with the model's standardization (SG_E_STATE if none is set) and,
+ * when ms_dev is given, the targets T as in sg_mlp_fit_data (held-out samples). */
+sg_status sg_mlp_standardize(sg_mlp m, const float* X_dev, const double* ms_dev, int64_t n, float* Xn_dev, float* T_dev);
+/* Save the cost model (parameters, Adam moments and step, standardization) to a file, and
+ * create a model on `ctx` from one; training resumes where it stopped.  SG_E_STATE when the
+ * model has no standardization yet; SG_E_INVALID for an unreadable or foreign file. */
+sg_status sg_mlp_save(sg_mlp m, const char* path);
+sg_status sg_mlp_load(sg_ctx ctx, const char* path, sg_mlp* out);
+
+/* ---- the autotuner's timing database ------------------------------------------------------ */
+
+typedef struct sg_tunedb_s* sg_tunedb;
+/* Key of a program on its context's device: a 64-bit hash of its operations, constants,
+ * element types, lengths (not the data), clauses, split points and the context's mode, with
+ * the device's architecture and compute-unit count.  Equal programs on equal devices get
+ * equal keys in every process. */
+sg_status sg_program_key(sg_program p, uint64_t* key);
+/* Open (creating if absent) an append-only text file of autotuner timings, one record per
+ * line: "sgtune1 <key hex> <block> <unroll> <substeps> <split> <ms>"; the last record of a
+ * (key, plan) pair wins.  SG_E_INVALID for a malformed record (its line is named) or a file
+ * that cannot be appended to. */
+sg_status sg_tunedb_open(sg_ctx ctx, const char* path, sg_tunedb* out);
+sg_status sg_tunedb_close(sg_tunedb db);
+/* Records read and appended so far, and distinct (key, plan) pairs. */
+sg_status sg_tunedb_records(sg_tunedb db, int64_t* records, int64_t* distinct);
+/* *ms = the recorded time of (key, plan), or -1 when there is none. */
+sg_status sg_tunedb_lookup(sg_tunedb db, uint64_t key, const sg_plan* plan, double* ms);
+/* Append one record (flushed before the call returns). */
+sg_status sg_tunedb_record(sg_tunedb db, uint64_t key, const sg_plan* plan, double ms);
+/* sg_autotune through the database: plans with a recorded time for this program's key are
+ * not timed again; the others are timed (as sg_program_time_plans) and appended.  Sets the
+ * fastest plan on the program; *best its index, ms_out (n, optional) every plan's time,
+ * *measured (optional) how many plans were timed now. */
+sg_status sg_autotune_db(sg_program p, sg_tunedb db, const sg_plan* plans, int32_t n, int32_t reps, int32_t* best,
+                         double* ms_out, int32_t* measured);
 
 /* ---- host-side checks of device arithmetic (no GPU needed) ------------------------------ */
 

@@ -81,3 +81,23 @@ def adam_train(p, X, T, batch=128, epochs=1, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8
             p = p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
         losses.append(tot / n)
     return p, losses
+
+
+def fit_data(X, ms=None):
+    """Training data of the cost model: per feature the mean and the population standard
+    deviation of the raw features in float64 (scale 1 where that deviation is at most 1e-6),
+    the minimum and the maximum; both rounded to binary32; standardized features
+    (x - mean) / scale in binary32 operations; targets RN32(log(1000 ms)) (log of the run time
+    in microseconds).  Returns (mean, scale, lo, hi, Xn, T or None)."""
+    X = np.asarray(X, dtype=np.float32)
+    X64 = X.astype(np.float64)
+    mean64 = X64.mean(axis=0)
+    std64 = np.sqrt(((X64 - mean64) ** 2).mean(axis=0))
+    mean = mean64.astype(np.float32)
+    scale = np.where(std64 > 1e-6, std64, 1.0).astype(np.float32)
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    Xn = ((X - mean) / scale).astype(np.float32)  # binary32 subtract, then divide
+    T = None
+    if ms is not None:
+        T = np.log(np.asarray(ms, np.float64) * 1000.0).astype(np.float32)
+    return mean, scale, lo, hi, Xn, T

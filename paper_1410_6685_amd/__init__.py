@@ -110,7 +110,15 @@ def _sig(lib):
         "sg_mlp_grad": [H, H, H, c_int32, H, P(c_double)],
         "sg_mlp_train": [H, H, H, c_int64, c_int32, c_int32, ctypes.c_float, P(c_double)],
         "sg_mlp_predict": [H, H, c_int64, H], "sg_mlp_set_norm": [H, H, H, H, H],
+        "sg_mlp_get_norm": [H, H, H, H, H],
         "sg_select_plan": [H, H, H, c_int32, ctypes.c_float, P(c_int32), H, P(c_int32)],
+        "sg_mlp_fit_data": [H, H, H, c_int64, H, H], "sg_mlp_standardize": [H, H, H, c_int64, H, H],
+        "sg_mlp_save": [H, c_char_p], "sg_mlp_load": [H, c_char_p, P(H)],
+        "sg_program_key": [H, P(ctypes.c_uint64)], "sg_tunedb_open": [H, c_char_p, P(H)], "sg_tunedb_close": [H],
+        "sg_tunedb_records": [H, P(c_int64), P(c_int64)],
+        "sg_tunedb_lookup": [H, ctypes.c_uint64, H, P(c_double)],
+        "sg_tunedb_record": [H, ctypes.c_uint64, H, c_double],
+        "sg_autotune_db": [H, H, H, c_int32, c_int32, P(c_int32), P(c_double), P(c_int32)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -431,12 +439,27 @@ class Program:
         _check(load().sg_program_time_plans(self.h, arr, len(plans), reps, ms), self.ctx.h)
         return list(ms)
 
-    def autotune(self, plans, reps: int = 3):
+    def autotune(self, plans, reps: int = 3, db: "TuneDB | None" = None):
+        """Time every plan and keep the fastest; with a timing database, plans already timed
+        for this program's key are read from it and new timings appended.  Returns (best
+        index, times in ms) -- and, with a database, the number of plans timed now."""
         arr = plans_array(plans)
         ms = (c_double * len(plans))()
         best = c_int32()
-        _check(load().sg_autotune(self.h, arr, len(plans), reps, byref(best), ms), self.ctx.h)
-        return best.value, list(ms)
+        if db is None:
+            _check(load().sg_autotune(self.h, arr, len(plans), reps, byref(best), ms), self.ctx.h)
+            return best.value, list(ms)
+        measured = c_int32()
+        _check(load().sg_autotune_db(self.h, db.h, arr, len(plans), reps, byref(best), ms, byref(measured)),
+               self.ctx.h)
+        return best.value, list(ms), measured.value
+
+    def key(self) -> int:
+        """Program key of the timing database (operations, constants, types, lengths, clauses,
+        mode and device)."""
+        k = ctypes.c_uint64()
+        _check(load().sg_program_key(self.h, byref(k)), self.ctx.h)
+        return k.value
 
     def launch(self):
         """Enqueue one execution without waiting (collect it with wait(), oldest first)."""
@@ -539,6 +562,60 @@ class Mlp:
         torch.cuda.synchronize()
         return Y
 
+    def fit_data(self, X, ms=None):
+        """Fit the standardization on raw features X (CUDA float32, n x 24) on the device and
+        return (standardized features, targets log(us) or None); ms: CUDA float64 (n)."""
+        import torch
+        _features_tensor(X, "fit_data")
+        n = X.shape[0]
+        Xn = torch.empty_like(X)
+        T = None
+        if ms is not None:
+            if not isinstance(ms, torch.Tensor) or not ms.is_cuda or ms.dtype != torch.float64 \
+                    or not ms.is_contiguous() or ms.numel() != n:
+                raise ValueError("fit_data: ms must be a contiguous CUDA float64 tensor of n entries")
+            T = torch.empty(n, dtype=torch.float32, device=X.device)
+        _check(load().sg_mlp_fit_data(self.h, c_void_p(X.data_ptr()), c_void_p(ms.data_ptr() if ms is not None else 0),
+                                      n, c_void_p(Xn.data_ptr()), c_void_p(T.data_ptr() if T is not None else 0)),
+               self.ctx.h)
+        return Xn, T
+
+    def standardize(self, X, ms=None):
+        """Standardize features with the fitted standardization; with ms (CUDA float64) also
+        return the targets log(us).  Returns Xn, or (Xn, T)."""
+        import torch
+        _features_tensor(X, "standardize")
+        n = X.shape[0]
+        Xn = torch.empty_like(X)
+        T = None
+        if ms is not None:
+            if not isinstance(ms, torch.Tensor) or not ms.is_cuda or ms.dtype != torch.float64 \
+                    or not ms.is_contiguous() or ms.numel() != n:
+                raise ValueError("standardize: ms must be a contiguous CUDA float64 tensor of n entries")
+            T = torch.empty(n, dtype=torch.float32, device=X.device)
+        _check(load().sg_mlp_standardize(self.h, c_void_p(X.data_ptr()), c_void_p(ms.data_ptr() if ms is not None else 0),
+                                         n, c_void_p(Xn.data_ptr()), c_void_p(T.data_ptr() if T is not None else 0)),
+               self.ctx.h)
+        return Xn if ms is None else (Xn, T)
+
+    def save(self, path: str):
+        _check(load().sg_mlp_save(self.h, os.fsencode(path)), self.ctx.h)
+
+    @classmethod
+    def load_file(cls, ctx: "Context", path: str) -> "Mlp":
+        m = cls.__new__(cls)
+        m.ctx = ctx
+        m.h = c_void_p()
+        _check(load().sg_mlp_load(ctx.h, os.fsencode(path), byref(m.h)), ctx.h)
+        return m
+
+    def get_norm(self):
+        """(mean, scale, lo, hi) of the model's standardization, float32 arrays of 24."""
+        import numpy as np
+        arrs = [np.empty(24, np.float32) for _ in range(4)]
+        _check(load().sg_mlp_get_norm(self.h, *[a.ctypes.data for a in arrs]), self.ctx.h)
+        return tuple(arrs)
+
     def set_norm(self, mean, scale, lo, hi):
         import numpy as np
         arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (mean, scale, lo, hi)]
@@ -553,6 +630,38 @@ class Mlp:
         _check(load().sg_select_plan(self.h, program.h, arr, len(plans), margin, byref(best), pred.ctypes.data,
                                      byref(fb)), self.ctx.h)
         return best.value, pred, bool(fb.value)
+
+
+class TuneDB:
+    """The autotuner's append-only timing file (sg_tunedb_*)."""
+
+    def __init__(self, ctx: "Context", path: str):
+        self.ctx = ctx
+        self.h = c_void_p()
+        _check(load().sg_tunedb_open(ctx.h, os.fsencode(path), byref(self.h)), ctx.h)
+
+    def close(self):
+        if self.h and _lib is not None:
+            _lib.sg_tunedb_close(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def records(self):
+        r, d = c_int64(), c_int64()
+        _check(load().sg_tunedb_records(self.h, byref(r), byref(d)), self.ctx.h)
+        return r.value, d.value
+
+    def lookup(self, key: int, plan):
+        p = plan if isinstance(plan, Plan) else Plan(*plan)
+        ms = c_double()
+        _check(load().sg_tunedb_lookup(self.h, ctypes.c_uint64(key), byref(p), byref(ms)), self.ctx.h)
+        return None if ms.value < 0 else ms.value
+
+    def record(self, key: int, plan, ms: float):
+        p = plan if isinstance(plan, Plan) else Plan(*plan)
+        _check(load().sg_tunedb_record(self.h, ctypes.c_uint64(key), byref(p), ms), self.ctx.h)
 
 
 class Batch:

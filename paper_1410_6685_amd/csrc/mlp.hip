@@ -181,6 +181,67 @@ __global__ __launch_bounds__(256) void mlp_predict_kernel(const float* __restric
     Y[s] = y;
 }
 
+
+// Training data of the cost model.  One block per feature column: the column's mean and
+// population standard deviation (two passes, float64, each thread's strided partial sums
+// added lanes-then-waves in a fixed order), minimum and maximum.  stats[k] = {mean, std, lo,
+// hi} as doubles.
+__global__ __launch_bounds__(256) void mlp_colstats_kernel(const float* __restrict__ X, int64_t n,
+                                                           double* __restrict__ stats) {
+    __shared__ double red[4];
+    __shared__ float rmin[4], rmax[4];
+    const int k = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto block_sum = [&](double v) -> double {
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+        return t;
+    };
+    double s = 0.0;
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const float x = X[i * MI + k];
+        s += (double)x;
+        lo = fminf(lo, x);
+        hi = fmaxf(hi, x);
+    }
+    const double mean = block_sum(s) / (double)n;
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double d = (double)X[i * MI + k] - mean;
+        q += d * d;
+    }
+    const double var = block_sum(q) / (double)n;
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o));
+        hi = fmaxf(hi, __shfl_xor(hi, o));
+    }
+    if (lane == 0) { rmin[wave] = lo; rmax[wave] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        stats[4 * k + 0] = mean;
+        stats[4 * k + 1] = __builtin_sqrt(var);
+        stats[4 * k + 2] = fminf(fminf(rmin[0], rmin[1]), fminf(rmin[2], rmin[3]));
+        stats[4 * k + 3] = fmaxf(fmaxf(rmax[0], rmax[1]), fmaxf(rmax[2], rmax[3]));
+    }
+}
+
+// Xn = (X - mean) / scale per feature (float32 operations), T = log(1000 ms) (microseconds,
+// computed in float64 and rounded to float32).
+__global__ __launch_bounds__(256) void mlp_standardize_kernel(const float* __restrict__ X, const double* __restrict__ ms,
+                                                              int64_t n, const float* __restrict__ mean,
+                                                              const float* __restrict__ scale, float* __restrict__ Xn,
+                                                              float* __restrict__ T) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n * MI) {
+        const int k = (int)(i % MI);
+        Xn[i] = (X[i] - mean[k]) / scale[k];
+    }
+    if (ms && i < n) T[i] = (float)log(ms[i] * 1000.0);
+}
+
 }  // namespace sg
 
 using namespace sgrt;
@@ -299,6 +360,89 @@ sg_status sg_mlp_predict(sg_mlp m, const float* X_dev, int64_t n, float* Y_dev) 
     const unsigned grid = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(sg::mlp_predict_kernel, dim3(grid), dim3(256), 0, ctx->stream, m->P, X_dev, n, Y_dev);
     SG_HIP(ctx, hipGetLastError());
+    return SG_OK;
+}
+
+// Training data of the cost model, prepared on the device: fit the standardization on the
+// raw features X (n x 24), then write the standardized features Xn and, when ms is given, the
+// targets log(run time in microseconds).
+sg_status sg_mlp_fit_data(sg_mlp m, const float* X_dev, const double* ms_dev, int64_t n, float* Xn_dev, float* T_dev) {
+    if (!m || !X_dev || !Xn_dev || n < 1 || (ms_dev && !T_dev))
+        return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_fit_data: bad argument");
+    sg_ctx_s* ctx = m->ctx;
+    if (sg_status st = check_device_range(ctx, X_dev, (size_t)n * sg::MI * 4, "mlp_fit_data X")) return st;
+    if (sg_status st = check_device_range(ctx, Xn_dev, (size_t)n * sg::MI * 4, "mlp_fit_data Xn")) return st;
+    if (ms_dev) {
+        if (sg_status st = check_device_range(ctx, ms_dev, (size_t)n * 8, "mlp_fit_data ms")) return st;
+        if (sg_status st = check_device_range(ctx, T_dev, (size_t)n * 4, "mlp_fit_data T")) return st;
+    }
+    // statistics (24 x 4 doubles), then the float32 mean and scale the kernels and the
+    // selector use
+    void* w = dev_alloc(ctx, sg::MI * 4 * sizeof(double) + 2 * sg::MI * sizeof(float));
+    if (!w) return fail(ctx, SG_E_OOM, "mlp_fit_data: workspace");
+    double* stats = (double*)w;
+    float* msd = (float*)(stats + sg::MI * 4);
+    double h[sg::MI * 4];
+    hipLaunchKernelGGL(sg::mlp_colstats_kernel, dim3(sg::MI), dim3(256), 0, ctx->stream, X_dev, n, stats);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        dev_free(ctx, w);
+        return hip_fail(ctx, e, "mlp_fit_data: statistics");
+    }
+    float mean[sg::MI], scale[sg::MI], lo[sg::MI], hi[sg::MI], both[2 * sg::MI];
+    for (int k = 0; k < sg::MI; ++k) {
+        mean[k] = (float)h[4 * k];
+        // a constant feature keeps scale 1 (it standardizes to 0)
+        scale[k] = h[4 * k + 1] > 1e-6 ? (float)h[4 * k + 1] : 1.0f;
+        lo[k] = (float)h[4 * k + 2];
+        hi[k] = (float)h[4 * k + 3];
+        both[k] = mean[k];
+        both[sg::MI + k] = scale[k];
+    }
+    (void)sg_mlp_set_norm(m, mean, scale, lo, hi);
+    e = hipMemcpyAsync(msd, both, sizeof(both), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        const int64_t tot = n * sg::MI;
+        hipLaunchKernelGGL(sg::mlp_standardize_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream,
+                           X_dev, ms_dev, n, msd, msd + sg::MI, Xn_dev, T_dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, w);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp_fit_data: standardize");
+    return SG_OK;
+}
+
+// Standardized features of n samples with the model's fitted standardization (and targets).
+sg_status sg_mlp_standardize(sg_mlp m, const float* X_dev, const double* ms_dev, int64_t n, float* Xn_dev, float* T_dev) {
+    if (!m || !X_dev || !Xn_dev || n < 0 || (ms_dev && !T_dev))
+        return fail(m ? m->ctx : nullptr, SG_E_INVALID, "mlp_standardize: bad argument");
+    sg_ctx_s* ctx = m->ctx;
+    if (!m->norm_set) return fail(ctx, SG_E_STATE, "mlp_standardize: the model has no standardization");
+    if (n == 0) return SG_OK;
+    if (sg_status st = check_device_range(ctx, X_dev, (size_t)n * sg::MI * 4, "mlp_standardize X")) return st;
+    if (sg_status st = check_device_range(ctx, Xn_dev, (size_t)n * sg::MI * 4, "mlp_standardize Xn")) return st;
+    if (ms_dev) {
+        if (sg_status st = check_device_range(ctx, ms_dev, (size_t)n * 8, "mlp_standardize ms")) return st;
+        if (sg_status st = check_device_range(ctx, T_dev, (size_t)n * 4, "mlp_standardize T")) return st;
+    }
+    float* msd = (float*)dev_alloc(ctx, 2 * sg::MI * sizeof(float));
+    if (!msd) return fail(ctx, SG_E_OOM, "mlp_standardize: workspace");
+    float both[2 * sg::MI];
+    std::memcpy(both, m->mean, sizeof(m->mean));
+    std::memcpy(both + sg::MI, m->scale, sizeof(m->scale));
+    hipError_t e = hipMemcpyAsync(msd, both, sizeof(both), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        const int64_t tot = n * sg::MI;
+        hipLaunchKernelGGL(sg::mlp_standardize_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream,
+                           X_dev, ms_dev, n, msd, msd + sg::MI, Xn_dev, T_dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, msd);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp_standardize");
     return SG_OK;
 }
 

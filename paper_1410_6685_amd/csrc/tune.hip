@@ -247,6 +247,16 @@ sg_status sg_mlp_set_norm(sg_mlp m, const float* mean24, const float* scale24, c
     return SG_OK;
 }
 
+sg_status sg_mlp_get_norm(sg_mlp m, float* mean24, float* scale24, float* lo24, float* hi24) {
+    if (!m || !mean24 || !scale24 || !lo24 || !hi24) return fail(nullptr, SG_E_INVALID, "mlp_get_norm: NULL argument");
+    if (!m->norm_set) return fail(m->ctx, SG_E_STATE, "mlp_get_norm: the model has no standardization");
+    std::memcpy(mean24, m->mean, sizeof(m->mean));
+    std::memcpy(scale24, m->scale, sizeof(m->scale));
+    std::memcpy(lo24, m->lo, sizeof(m->lo));
+    std::memcpy(hi24, m->hi, sizeof(m->hi));
+    return SG_OK;
+}
+
 // Predict every candidate's log run time and keep the argmin.  *fallback = 1 when a raw
 // feature is outside the training range or the best two predictions differ by less than
 // `margin` (log units); the plan is then left unchanged for the autotuner to decide.

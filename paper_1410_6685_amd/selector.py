@@ -39,16 +39,19 @@ class Timings:
     ms: list = field(default_factory=list)       # per chain: (plans,) float64 milliseconds
     plans: list = field(default_factory=list)    # per chain: list of plan tuples
 
-    def flat(self):
-        X = np.concatenate(self.X).astype(np.float32)
-        y = np.log(np.concatenate(self.ms) * 1e3).astype(np.float32)  # log(microseconds)
-        return X, y
+    def device(self):
+        """All samples as CUDA tensors: raw features (n x 24 float32), times (n float64 ms)."""
+        import torch
+        X = torch.from_numpy(np.ascontiguousarray(np.concatenate(self.X), dtype=np.float32)).cuda()
+        ms = torch.from_numpy(np.ascontiguousarray(np.concatenate(self.ms), dtype=np.float64)).cuda()
+        return X, ms
 
 
-def collect(programs, reps: int = 3, progress=None, rejected=None) -> Timings:
-    """Time every candidate plan of every program (the autotuner's measurements).  A plan the
-    planner refuses for a chain is left out of that chain's candidates (and listed in
-    `rejected` as (chain index, plan, message) when a list is given)."""
+def collect(programs, reps: int = 3, progress=None, rejected=None, db=None) -> Timings:
+    """Time every candidate plan of every program (the autotuner's measurements; with a timing
+    database, plans already timed for a program's key are read from it).  A plan the planner
+    refuses for a chain is left out of that chain's candidates (and listed in `rejected` as
+    (chain index, plan, message) when a list is given)."""
     from . import SafeGPUError
 
     out = Timings()
@@ -62,7 +65,10 @@ def collect(programs, reps: int = 3, progress=None, rejected=None) -> Timings:
                 if rejected is not None:
                     rejected.append((i, p, str(e)))
         X = np.array(feats, np.float32)
-        ms = np.array(prog.time_plans(plans, reps), np.float64)
+        if db is None:
+            ms = np.array(prog.time_plans(plans, reps), np.float64)
+        else:
+            ms = np.array(prog.autotune(plans, reps, db=db)[1], np.float64)
         out.X.append(X)
         out.ms.append(ms)
         out.plans.append(plans)
@@ -71,38 +77,19 @@ def collect(programs, reps: int = 3, progress=None, rejected=None) -> Timings:
     return out
 
 
-@dataclass
-class Normalizer:
-    mean: np.ndarray
-    scale: np.ndarray
-    lo: np.ndarray
-    hi: np.ndarray
-
-    @staticmethod
-    def fit(X: np.ndarray) -> "Normalizer":
-        mean = X.mean(axis=0)
-        scale = X.std(axis=0)
-        scale = np.where(scale > 1e-6, scale, 1.0)
-        return Normalizer(mean.astype(np.float32), scale.astype(np.float32), X.min(axis=0), X.max(axis=0))
-
-    def apply(self, X: np.ndarray) -> np.ndarray:
-        return ((X - self.mean) / self.scale).astype(np.float32)
-
-
 def train(ctx, timings: Timings, init_params, epochs: int = 60, batch: int = 128, lr: float = 2e-3,
           seed: int = 0):
-    """Fit the cost model on the device.  Returns (model, normalizer, per-epoch losses)."""
+    """Fit the cost model on the device: the library fits the standardization and forms the
+    log-time targets (sg_mlp_fit_data), then trains in a seeded sample order.  Returns
+    (model, per-epoch losses)."""
     import torch
 
-    X, y = timings.flat()
-    norm = Normalizer.fit(X)
-    perm = np.random.Generator(np.random.PCG64(seed)).permutation(len(y))
-    Xn = torch.from_numpy(norm.apply(X)[perm]).cuda()
-    yt = torch.from_numpy(y[perm]).cuda()
+    X, ms = timings.device()
     net = Mlp(ctx, init_params)
-    losses = net.train(Xn, yt, batch=batch, epochs=epochs, lr=lr)
-    net.set_norm(norm.mean, norm.scale, norm.lo, norm.hi)
-    return net, norm, losses
+    Xn, T = net.fit_data(X, ms)
+    perm = torch.from_numpy(np.random.Generator(np.random.PCG64(seed)).permutation(T.numel())).cuda()
+    losses = net.train(Xn[perm].contiguous(), T[perm].contiguous(), batch=batch, epochs=epochs, lr=lr)
+    return net, losses
 
 
 @dataclass
