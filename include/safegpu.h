@@ -165,6 +165,18 @@ sg_status sg_fn_mul_c(double c, sg_fn* out);
 /* One of sg_fn_kind (sqrt as in the project example of Section 3.2; exp correctly rounded).
  * SG_E_INVALID for an unknown kind. */
 sg_status sg_fn_unary(sg_fn_kind kind, sg_fn* out);
+/* A user element function written as an arithmetic expression in x (an agent of type
+ * FUNCTION, Section 3.2, which the paper compiles into the generated kernel, Section 5):
+ *     expr := term (("+" | "-") term)*     term := unary (("*" | "/") unary)*
+ *     unary := "-" unary | primary
+ *     primary := number | "x" | "(" expr ")" | ("sqrt" | "abs" | "exp") "(" expr ")"
+ * Literals are rounded to binary32 (through their float64 value) when the function is made;
+ * every operation gives the correctly rounded binary32 result on binary32 operands, along the
+ * tree the grammar gives.  Defined on f32 (SG_E_DTYPE otherwise).  SG_E_INVALID with the
+ * offset of the first error for text outside the grammar.  A map by an expression needs
+ * registers of the streaming pass for its intermediate values; a chain that runs out of them
+ * gets SG_E_UNSUPPORTED (a split point helps). */
+sg_status sg_fn_expr(const char* text, sg_fn* out);
 /* first f, then g (one agent made of two, evaluated as one expression, Figure 3) */
 sg_status sg_fn_compose(sg_fn f, sg_fn g, sg_fn* out);
 sg_status sg_fn_release(sg_fn f);
@@ -425,6 +437,11 @@ sg_status sg_autotune_db(sg_program p, sg_tunedb db, const sg_plan* plans, int32
 /* Evaluate the device code's correctly rounded binary32 exp on the host for n values;
  * *slow receives how many took the double-double path.  For tests. */
 sg_status sg_host_exp_rn(const float* t, float* out, int64_t n, int64_t* slow);
+/* Compile an expression agent (sg_fn_expr) into the register program a map gives it -- x and
+ * the result in register 0, registers 1 .. registers-1 free -- and run that program on the
+ * host in binary32 for n values; *nops = the program's length.  SG_E_UNSUPPORTED when the
+ * expression needs more registers.  For tests of the expression compiler. */
+sg_status sg_host_expr_run(const char* text, int32_t registers, const float* x, float* out, int64_t n, int32_t* nops);
 
 #ifdef __cplusplus
 }

@@ -80,7 +80,7 @@ def _sig(lib):
         "sg_vector_from_host": [H, c_int, H, c_int64, P(H)],
         "sg_matrix_from_host": [H, c_int, H, c_int64, c_int64, P(H)],
         "sg_fn_affine": [c_double, c_double, P(H)], "sg_fn_add_c": [c_double, P(H)], "sg_fn_mul_c": [c_double, P(H)],
-        "sg_fn_unary": [c_int, P(H)], "sg_fn_compose": [H, H, P(H)], "sg_fn_release": [H],
+        "sg_fn_unary": [c_int, P(H)], "sg_fn_expr": [c_char_p, P(H)], "sg_fn_compose": [H, H, P(H)], "sg_fn_release": [H],
         "sg_pred_cmp": [c_int, c_double, P(H)], "sg_pred_isfinite": [P(H)], "sg_pred_in_range": [c_double, c_double, P(H)],
         "sg_pred_true": [P(H)], "sg_pred_and": [H, H, P(H)], "sg_pred_or": [H, H, P(H)], "sg_pred_not": [H, P(H)],
         "sg_pred_release": [H],
@@ -102,6 +102,7 @@ def _sig(lib):
         "sg_batch_run": [H, P(c_int32), P(Verdict), c_int32, P(c_int32)],
         "sg_batch_launch": [H], "sg_batch_release": [H],
         "sg_host_exp_rn": [H, H, c_int64, P(c_int64)],
+        "sg_host_expr_run": [c_char_p, c_int32, H, H, c_int64, P(c_int32)],
         "sg_program_split_candidates": [H, P(c_int32)], "sg_program_set_plan": [H, H],
         "sg_program_features": [H, H, P(ctypes.c_float)],
         "sg_program_time_plans": [H, H, c_int32, c_int32, P(c_double)],
@@ -160,6 +161,17 @@ def host_exp_rn(t):
     return out, slow.value
 
 
+def host_expr_run(text: str, x, registers: int = 5):
+    """Run an expression agent's register program (as a map would get it, with `registers`
+    registers) on the host; returns (float32 values, program length)."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty_like(x)
+    nops = c_int32()
+    _check(load().sg_host_expr_run(text.encode(), registers, x.ctypes.data, out.ctypes.data, x.size, byref(nops)))
+    return out, nops.value
+
+
 # ---------------------------------------------------------------------------------------------
 # agents
 
@@ -188,6 +200,11 @@ class Fn:
     def unary(name):
         h = c_void_p(); _check(load().sg_fn_unary(FN_UNARY[name], byref(h))); return Fn(h)
 
+    @staticmethod
+    def expr(text: str):
+        """A user element function written as an arithmetic expression in x."""
+        h = c_void_p(); _check(load().sg_fn_expr(text.encode(), byref(h))); return Fn(h)
+
     def then(self, g: "Fn"):
         h = c_void_p(); _check(load().sg_fn_compose(self.h, g.h, byref(h))); return Fn(h)
 
@@ -202,6 +219,8 @@ class Fn:
             return Fn.mul_c(float(fn[1]))
         if name == "compose":
             return Fn.from_spec(fn[1]).then(Fn.from_spec(fn[2]))
+        if name == "expr":
+            return Fn.expr(fn[1])
         return Fn.unary(name)
 
 

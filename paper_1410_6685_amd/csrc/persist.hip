@@ -60,6 +60,10 @@ void hash_fn(Hasher& H, const sg_fn_s* f) {
     H.val(f->a);
     H.val(f->b);
     if (f->kind == FK_COMPOSE) { hash_fn(H, f->f); hash_fn(H, f->g); }
+    if (f->kind == FK_EXPR) {
+        H.val(f->expr_root);
+        for (const ExprNode& e : *f->expr) { H.val(e.kind); H.val(e.c); H.val(e.a); H.val(e.b); }
+    }
 }
 
 void hash_pred(Hasher& H, const sg_pred_s* p) {

@@ -450,7 +450,11 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                             mv.code = MOV; mv.a = (uint8_t)ra; mv.dst = (uint8_t)rd;
                             prog.push_back(mv);
                         }
-                        emit_fn(prog, n->fn, rd, n->src[0]->dtype);
+                        // registers free for the map's duration (expression agents use them)
+                        std::vector<int> temps;
+                        for (int r = 0; r < NREG && (int)temps.size() < fn_temps(n->fn); ++r)
+                            if (!owner[r] && r != rd) temps.push_back(r);
+                        if (!emit_fn(prog, n->fn, rd, n->src[0]->dtype, temps)) { too_many = true; break; }
                     } break;
                     case OPN_ZIP: {
                         int ra = reg_of(n->src[0]), rb = reg_of(n->src[1]);

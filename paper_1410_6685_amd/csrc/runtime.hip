@@ -182,6 +182,7 @@ void release(sg_fn_s* f) {
     if (!f || --f->refs > 0) return;
     release(f->f);
     release(f->g);
+    delete f->expr;
     delete f;
 }
 void release(sg_pred_s* p) {
@@ -220,6 +221,9 @@ bool fn_out_dtype(const sg_fn_s* f, sg_dtype in, sg_dtype* out, std::string* why
             return fn_out_dtype(f->g, mid, out, why);
         }
         case FK_AFFINE: case FK_ADDC: case FK_MULC: *out = in; return true;
+        case FK_EXPR:
+            if (in != SG_F32) { *why = "expression functions are defined on f32"; return false; }
+            *out = SG_F32; return true;
         case FK_UNARY:
             switch ((int)f->a) {
                 case SG_FN_SQUARE: case SG_FN_NEG: case SG_FN_ABS: *out = in; return true;
@@ -237,8 +241,15 @@ bool fn_out_dtype(const sg_fn_s* f, sg_dtype in, sg_dtype* out, std::string* why
 
 inline int32_t to_i32(double c) { return (int32_t)(int64_t)c; }
 
+int fn_temps(const sg_fn_s* f) {
+    if (!f) return 0;
+    if (f->kind == FK_COMPOSE) return std::max(fn_temps(f->f), fn_temps(f->g));
+    if (f->kind == FK_EXPR) return expr_temps(*f->expr, f->expr_root);
+    return 0;
+}
+
 // emit the in-place ops applying f to register r (element type dt)
-void emit_fn(std::vector<SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt) {
+bool emit_fn(std::vector<SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt, const std::vector<int>& temps) {
     auto op = [&](uint8_t code, float c0 = 0.f, float c1 = 0.f) {
         SgOp o{};
         o.code = code; o.a = (uint8_t)r; o.dst = (uint8_t)r; o.c0.f = c0; o.c1.f = c1;
@@ -251,36 +262,39 @@ void emit_fn(std::vector<SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt) {
     };
     switch (f->kind) {
         case FK_COMPOSE: {
-            emit_fn(prog, f->f, r, dt);
+            if (!emit_fn(prog, f->f, r, dt, temps)) return false;
             sg_dtype mid;
             std::string why;
             fn_out_dtype(f->f, dt, &mid, &why);
-            emit_fn(prog, f->g, r, mid);
-        } return;
+            return emit_fn(prog, f->g, r, mid, temps);
+        }
+        case FK_EXPR:
+            return emit_expr(prog, *f->expr, f->expr_root, r, temps);
         case FK_AFFINE:
             if (dt == SG_F32) op(F_AFFINE, (float)f->a, (float)f->b);
             else opi(I_AFFINE, to_i32(f->a), to_i32(f->b));
-            return;
+            return true;
         case FK_ADDC:
             if (dt == SG_F32) op(F_ADDC, (float)f->a);
             else opi(I_ADDC, to_i32(f->a));
-            return;
+            return true;
         case FK_MULC:
             if (dt == SG_F32) op(F_MULC, (float)f->a);
             else opi(I_MULC, to_i32(f->a));
-            return;
+            return true;
         case FK_UNARY:
             switch ((int)f->a) {
-                case SG_FN_SQUARE: if (dt == SG_F32) op(F_SQUARE); else opi(I_SQUARE); return;
-                case SG_FN_NEG: if (dt == SG_F32) op(F_NEG); else opi(I_NEG); return;
-                case SG_FN_ABS: if (dt == SG_F32) op(F_ABS); else opi(I_ABS); return;
-                case SG_FN_SQRT: op(F_SQRT); return;
-                case SG_FN_SQRT_ABS: op(F_SQRT_ABS); return;
-                case SG_FN_EXP: op(F_EXP); return;
-                case SG_FN_EXP_NEG_SQ: op(F_EXP_NEG_SQ); return;
-                case SG_FN_I2F: op(I_TO_F); return;
+                case SG_FN_SQUARE: if (dt == SG_F32) op(F_SQUARE); else opi(I_SQUARE); return true;
+                case SG_FN_NEG: if (dt == SG_F32) op(F_NEG); else opi(I_NEG); return true;
+                case SG_FN_ABS: if (dt == SG_F32) op(F_ABS); else opi(I_ABS); return true;
+                case SG_FN_SQRT: op(F_SQRT); return true;
+                case SG_FN_SQRT_ABS: op(F_SQRT_ABS); return true;
+                case SG_FN_EXP: op(F_EXP); return true;
+                case SG_FN_EXP_NEG_SQ: op(F_EXP_NEG_SQ); return true;
+                case SG_FN_I2F: op(I_TO_F); return true;
             }
     }
+    return false;
 }
 
 // emit ops pushing predicate p evaluated on register r

@@ -47,6 +47,8 @@ enum OpCode : uint8_t {
     // value ops work in place: register a = f(a), or a = a (op) b
     F_AFFINE, F_ADDC, F_MULC, F_SQUARE, F_NEG, F_ABS, F_SQRT, F_SQRT_ABS, F_EXP, F_EXP_NEG_SQ,
     F_ADD, F_SUB, F_MUL, F_DIV,
+    // a = c0; a = a / c0; a = c0 / a (expression agents)
+    F_CONST, F_DIVC, F_RDIVC,
     // i32 value ops (wrap modulo 2^32)
     I_AFFINE, I_ADDC, I_MULC, I_SQUARE, I_NEG, I_ABS, I_ADD, I_SUB, I_MUL, I_TO_F,
     // predicates push one bit per element onto a 4-deep stack

@@ -18,7 +18,14 @@ namespace sgrt {
 enum NodeOp { OPN_INPUT = 0, OPN_MAP, OPN_ZIP, OPN_FILTER, OPN_REDUCE, OPN_MATMUL, OPN_QSORT, OPN_CONCAT, OPN_GAUSS,
               OPN_TRANSPOSE, OPN_MATVEC };
 enum NodeState { ST_NONE = 0, ST_COMPUTED = 1, ST_UNPUBLISHED = 2 };
-enum FnKind { FK_AFFINE = 0, FK_ADDC, FK_MULC, FK_UNARY, FK_COMPOSE };
+enum FnKind { FK_AFFINE = 0, FK_ADDC, FK_MULC, FK_UNARY, FK_COMPOSE, FK_EXPR };
+// node of an expression agent: x, a binary32 constant, a unary or a binary operation
+enum ExprKind : uint8_t { EX_X = 0, EX_CONST, EX_NEG, EX_ABS, EX_SQRT, EX_EXP, EX_ADD, EX_SUB, EX_MUL, EX_DIV };
+struct ExprNode {
+    uint8_t kind;
+    float c;   // EX_CONST
+    int a, b;  // operand nodes
+};
 enum PredKind { PK_CMP = 0, PK_FINITE, PK_RANGE, PK_TRUE, PK_AND, PK_OR, PK_NOT };
 
 struct Scratch {
@@ -73,6 +80,8 @@ struct sg_fn_s {
     double a = 0, b = 0;
     sg_fn_s* f = nullptr;
     sg_fn_s* g = nullptr;
+    std::vector<sgrt::ExprNode>* expr = nullptr;  // FK_EXPR: the parsed expression (owned)
+    int expr_root = -1;
 };
 
 struct sg_pred_s {
@@ -232,7 +241,14 @@ bool is_elementwise(const sg_node_s* n);
 // computed by a step of its own: matrix product, quicksort, concatenation
 inline bool is_kernel_node(const sg_node_s* n) { return n->op >= OPN_MATMUL; }
 bool is_collection(const sg_node_s* n);
-void emit_fn(std::vector<sg::SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt);
+// emit the ops applying f in place to register r; `temps` are registers free for the duration
+// (expression agents need them: fn_temps).  False when there are too few.
+bool emit_fn(std::vector<sg::SgOp>& prog, const sg_fn_s* f, int r, sg_dtype dt, const std::vector<int>& temps = {});
+int fn_temps(const sg_fn_s* f);
+// expression agents (expr.hip)
+bool parse_expr(const char* text, std::vector<ExprNode>& out, int* root, std::string* why);
+int expr_temps(const std::vector<ExprNode>& e, int root);
+bool emit_expr(std::vector<sg::SgOp>& prog, const std::vector<ExprNode>& e, int root, int r, const std::vector<int>& temps);
 void emit_pred(std::vector<sg::SgOp>& prog, const sg_pred_s* p, int r, sg_dtype dt);
 
 }  // namespace sgrt

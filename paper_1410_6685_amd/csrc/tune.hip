@@ -48,6 +48,16 @@ std::vector<sg_node_s*> split_candidates(sg_program_s* P) {
 int fn_count(const sg_fn_s* f, int kind_group) {
     if (!f) return 0;
     if (f->kind == FK_COMPOSE) return fn_count(f->f, kind_group) + fn_count(f->g, kind_group);
+    if (f->kind == FK_EXPR) {  // each operation of the expression in its group
+        int c = 0;
+        for (const ExprNode& e : *f->expr) {
+            const int g = e.kind == EX_SQRT ? 1 : e.kind == EX_EXP ? 2
+                        : (e.kind == EX_NEG || e.kind == EX_ABS) ? 3
+                        : (e.kind >= EX_ADD) ? 0 : -1;
+            c += g == kind_group;
+        }
+        return c;
+    }
     int g;
     if (f->kind == FK_AFFINE || f->kind == FK_ADDC || f->kind == FK_MULC) {
         g = 0;

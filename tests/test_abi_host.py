@@ -117,3 +117,75 @@ def test_device_exp_fast_path_sweep(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     total, hard, bad = (int(v) for v in r.stdout.split()[1::2])
     assert bad == 0 and total > 36_000_000 and hard < total // 500
+
+
+def random_expression(g, depth=0):
+    """A seeded expression of the agent grammar (mixed operators, literals, x, functions)."""
+    r = g.integers(0, 10) if depth < 5 else g.integers(0, 3)
+    if r == 0:
+        return "x"
+    if r == 1:
+        return repr(float(np.float32(g.uniform(-4, 4))))[:8].rstrip("-.e") or "1"
+    if r == 2:
+        return f"{g.integers(0, 20)}.{g.integers(0, 100)}"
+    if r == 3:
+        return f"-{random_expression(g, depth + 1)}"
+    if r == 4:
+        return f"{['sqrt', 'abs', 'exp'][g.integers(0, 3)]}({random_expression(g, depth + 1)})"
+    if r == 5:
+        return f"({random_expression(g, depth + 1)})"
+    return f"{random_expression(g, depth + 1)} {'+-*/'[g.integers(0, 4)]} {random_expression(g, depth + 1)}"
+
+
+def test_expression_programs_match_oracle(lib):
+    """The register programs the expression compiler gives a map (x and the result in one
+    register, intermediate values in the free ones) compute the oracle's values bit for bit,
+    with as many registers as the expression needs and with fewer (refused, never wrong)."""
+    from oracle.expr import apply_expr, parse
+    g = np.random.default_rng(12)
+    x = np.concatenate([W.normal_f32(400, 2, 3.0), np.array([0, -0.0, 1, -1, 0.5, 1e-40, np.inf, -np.inf, np.nan],
+                                                             np.float32)])
+    fixed = ["x", "2", "-x", "x*x", "x - x*x", "(x+1)*(x-1)/(x*x+2)", "1/(1+exp(-x))", "((x+1)*(x+2))*((x+3)*(x+4))",
+             "sqrt(abs(x)) - (x*0.25 - 1/(x+3))", "2 - (3 - (4 - x))", "(x*x+1)/((x+1)*(x-2) + (x*x)*(x+0.5))"]
+    exprs = fixed + [random_expression(g) for _ in range(300)]
+    refused = 0
+    for src in exprs:
+        try:
+            parse(src)
+        except ValueError:
+            continue
+        want = apply_expr(src, x)
+        ok_once = False
+        for regs in (1, 2, 3, 5, 8):
+            try:
+                got, nops = lib.host_expr_run(src, x, regs)
+            except lib.SafeGPUError as e:
+                assert e.status_name == "unsupported", (src, regs, e)
+                refused += 1
+                continue
+            ok_once = True
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)) or \
+                np.array_equal(np.isnan(got), np.isnan(want)) and \
+                np.array_equal(got[~np.isnan(got)].view(np.uint32), want[~np.isnan(want)].view(np.uint32)), (src, regs)
+        assert ok_once or src.count("(") > 20, src
+    assert refused > 0  # some expressions need more than one or two registers
+
+
+def test_expression_grammar_agrees_with_oracle(lib):
+    """sg_fn_expr accepts exactly the texts the oracle's parser accepts."""
+    from ctypes import byref, c_void_p
+    from oracle.expr import parse
+    L = lib.load()
+    texts = ["x", "x+", "(x", "x)", "2x", "1e3*x", "1e*x", ".5*x", "5.*x", "x**2", "sin(x)", "sqrt x", "exp((x))",
+             "--x", "x--x", "abs()", "", "   x   ", "x/0", "y", "3.0e-2+x", "x*-2", "(((x)))", "x..5"]
+    for t in texts:
+        try:
+            parse(t)
+            oracle_ok = True
+        except ValueError:
+            oracle_ok = False
+        h = c_void_p()
+        st = L.sg_fn_expr(t.encode(), byref(h))
+        assert (st == 0) == oracle_ok, (t, st)
+        if st == 0:
+            L.sg_fn_release(h)
