@@ -26,6 +26,7 @@ hipError_t sg_launch_gemm_f32(const float* A, const float* B, float* C, int64_t 
 hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
                                    int64_t N, int64_t K, int64_t nvec, double tol, double* work, InstResult* res,
                                    hipStream_t s);
+size_t sg_product_check_work_bytes(int64_t M, int64_t N, int64_t K);
 int sg_stream_occupancy(int unroll, bool inl, int block, size_t lds_bytes);
 hipError_t sg_launch_zero(uint64_t* p, int64_t n, hipStream_t s);
 
@@ -431,7 +432,7 @@ sg_status launch_program(sg_program_s* P, ExecSlot& es) {
             const double t = 2.0 * (double)K * u;
             const double tol = t / (1.0 - t) + std::ldexp(1.0, -40);
             if (nvec < 1 || nvec > 4) return fail(ctx, SG_E_UNSUPPORTED, "product check: 1 to 4 probe vectors");
-            void* work = dev_alloc(ctx, (size_t)(K + M) * 8 * sizeof(double));
+            void* work = dev_alloc(ctx, sg_product_check_work_bytes(M, N, K));
             if (!work) return fail(ctx, SG_E_OOM, "product check workspace");
             t_begin("product_check");
             hipError_t e = sg_launch_product_check((const float*)step.C->dev, (const float*)step.A->dev,

@@ -9,177 +9,220 @@
 //   1. BW = [B r_v | |B| |r_v|]          (K x 8)
 //   2. AW = [A BW_v | |A| BW_(4+v)]       (M x 8)
 //   3. C r_v, compared row by row with AW.
-// Each pass is a row-by-matrix product with an 8-column right-hand side read through the
-// caches; a wave works on two rows at a time, reading 16 bytes per lane.
+// Each pass is a row-by-matrix product with a narrow right-hand side.  The columns are split
+// into slices so that a 4096-row pass still has thousands of workgroups: a workgroup stages
+// its slice of the right-hand side in LDS (float64, 512 columns at a time), each of its four
+// waves reads four rows with 16-byte loads per lane and keeps 4 x 8 float64 sums per lane; a
+// second small kernel adds the slices' partial sums in slice order (and, for the last pass,
+// compares).  Every sum is taken in a fixed order, so results repeat from run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "sg_kernels.h"
 
 namespace sg {
 
-constexpr int PRW = 2;     // rows per wave
+constexpr int PC_RPW = 4;                 // rows per wave
+constexpr int PC_RPB = 4 * PC_RPW;        // rows per workgroup (4 waves)
+constexpr int PC_CH = 512;                // columns staged in LDS at a time
+constexpr int PC_TARGET_BLOCKS = 2048;    // workgroups a pass aims for
 
-__device__ __forceinline__ double wsum(double v) {
+__device__ __forceinline__ double pc_wsum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// out[i][c] = sum_j f_c(X[i][j]) W[j][c], f_c(x) = x for c < 4 and |x| for c >= 4 (NW = 8).
-// W comes from R (nvec x cols floats; column c is r_c for c < 4, |r_(c-4)| for c >= 4) or from
-// a cols x 8 double matrix Wd.  With cmp != null (NW = 4) the rows are compared with cmp.
-// W (at most cols x 8 doubles) is read directly and stays in the caches; each lane owns the
-// columns 4 lane + 256 k, taken in increasing order, and two of its column groups are loaded
-// before either is used, so a wave keeps several loads of X and W in flight.
+// part[slice][row][c] = sum over the slice's columns j of f_c(X[row][j]) W[j][c], with
+// f_c(x) = x for c < 4 and |x| for c >= 4.  W[j] is [r_0..r_3, |r_0|..|r_3|][j] taken from R
+// (nvec x cols floats; missing probes are zero) when Wd is null, else row j of the cols x 8
+// float64 matrix Wd.  NW = 4 computes the first four columns only.
 template <int NW>
-__global__ __launch_bounds__(256) void rowdot_kernel(const float* __restrict__ X, int64_t rows, int64_t cols,
-                                                     const float* __restrict__ R, int nvec,
-                                                     const double* __restrict__ Wd, double* __restrict__ out,
-                                                     const double* __restrict__ cmp, double tol,
-                                                     InstResult* res, int zero_res) {
+__global__ __launch_bounds__(256) void pc_part(const float* __restrict__ X, int64_t rows, int64_t cols,
+                                               const float* __restrict__ R, int nvec,
+                                               const double* __restrict__ Wd, int64_t slice_w,
+                                               double* __restrict__ part, InstResult* res, int zero_res) {
+    __shared__ __align__(16) double w[NW][PC_CH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (zero_res && blockIdx.x == 0 && tid == 0) {
+    if (zero_res && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
         res->slot[0] = 0;
         res->sum[0] = 0.0;
         res->err = 0;
     }
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * PRW;
-    double acc[PRW][NW];
+    const int64_t row0 = (int64_t)blockIdx.x * PC_RPB + wave * PC_RPW;
+    const int64_t s0 = (int64_t)blockIdx.y * slice_w, s1 = std::min<int64_t>(cols, s0 + slice_w);
+    const bool vec = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    double acc[PC_RPW][NW];
 #pragma unroll
-    for (int r = 0; r < PRW; ++r)
+    for (int r = 0; r < PC_RPW; ++r)
 #pragma unroll
         for (int c = 0; c < NW; ++c) acc[r][c] = 0.0;
-    const bool vec = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0) && (R == nullptr || (uintptr_t)R % 16 == 0);
 
-    // one group: columns j..j+3 of this lane's rows, and the matching rows of W
-    struct Group {
-        float x[PRW][4];
-        double w[4][NW];
-    };
-    auto load = [&](int64_t j, Group& g) {
-        const bool full = vec && j + 3 < cols;
+    for (int64_t c0 = s0; c0 < s1; c0 += PC_CH) {
+        const int cw = (int)std::min<int64_t>(PC_CH, s1 - c0);
+        // this chunk's rows of X: columns c0 + 4 lane + 256 g (+0..3), g = 0, 1
+        float x[2][PC_RPW][4];
 #pragma unroll
-        for (int r = 0; r < PRW; ++r) {
-            const int64_t row = row0 + r;
-            const float* xp = X + row * cols + j;
-            if (row < rows && full) {
-                const float4 v = *(const float4*)xp;
-                g.x[r][0] = v.x; g.x[r][1] = v.y; g.x[r][2] = v.z; g.x[r][3] = v.w;
+        for (int g = 0; g < 2; ++g) {
+            const int jl = 4 * lane + 256 * g;
+#pragma unroll
+            for (int r = 0; r < PC_RPW; ++r) {
+                const int64_t row = row0 + r;
+                const float* xp = X + row * cols + c0 + jl;
+                if (row < rows && vec && jl + 3 < cw) {
+                    const float4 v = *(const float4*)xp;
+                    x[g][r][0] = v.x; x[g][r][1] = v.y; x[g][r][2] = v.z; x[g][r][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) x[g][r][q] = (row < rows && jl + q < cw) ? xp[q] : 0.f;
+                }
+            }
+        }
+        __syncthreads();  // the previous chunk's right-hand side is no longer read
+        // stored transposed (w[c][j]): a lane's four consecutive columns are one contiguous
+        // 32-byte run, and a wave's reads of one c cover 2 KiB contiguously (no bank conflicts)
+        for (int j = tid; j < PC_CH; j += 256) {
+            if (j >= cw) {
+#pragma unroll
+                for (int c = 0; c < NW; ++c) w[c][j] = 0.0;
+            } else if (Wd) {
+#pragma unroll
+                for (int c = 0; c < NW; ++c) w[c][j] = Wd[(c0 + j) * 8 + c];
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) g.x[r][q] = (row < rows && j + q < cols) ? xp[q] : 0.f;
-            }
-        }
-        if (Wd) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < NW; ++c) g.w[q][c] = j + q < cols ? Wd[(j + q) * 8 + c] : 0.0;
-        } else {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float rv[4] = {0.f, 0.f, 0.f, 0.f};
-                if (v < nvec) {
-                    const float* rp = R + (int64_t)v * cols + j;
-                    if (full) {
-                        const float4 t = *(const float4*)rp;
-                        rv[0] = t.x; rv[1] = t.y; rv[2] = t.z; rv[3] = t.w;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) rv[q] = j + q < cols ? rp[q] : 0.f;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    g.w[q][v] = (double)rv[q];
-                    if (NW == 8) g.w[q][(v + 4) % NW] = (double)__builtin_fabsf(rv[q]);
+                for (int v = 0; v < 4; ++v) {
+                    const float rv = v < nvec ? R[(int64_t)v * cols + c0 + j] : 0.f;
+                    w[v][j] = (double)rv;
+                    if (NW == 8) w[(v + 4) % NW][j] = (double)__builtin_fabsf(rv);
                 }
             }
         }
-    };
-    auto use = [&](int64_t j, const Group& g) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (j + q >= cols) break;
-#pragma unroll
-            for (int r = 0; r < PRW; ++r) {
-                const double xv = (double)g.x[r][q];
-                const double ax = xv < 0 ? -xv : xv;
-#pragma unroll
-                for (int c = 0; c < NW; ++c) acc[r][c] += (c < 4 ? xv : ax) * g.w[q][c];
-            }
-        }
-    };
-    int64_t j = 4 * lane;
-    for (; j + 256 < cols; j += 512) {
-        Group g0, g1;
-        load(j, g0);
-        load(j + 256, g1);
-        use(j, g0);
-        use(j + 256, g1);
-    }
-    if (j < cols) {
-        Group g0;
-        load(j, g0);
-        use(j, g0);
-    }
-    // the largest ratio |e| / b of the block goes out with one atomic (nonnegative doubles
-    // order as their bit patterns); violations, rare, each with their own
-    uint64_t worst = 0;
-#pragma unroll
-    for (int r = 0; r < PRW; ++r) {
-        const int64_t row = row0 + r;
-        double tot[NW];
-#pragma unroll
-        for (int c = 0; c < NW; ++c) tot[c] = wsum(acc[r][c]);
-        if (lane != 0 || row >= rows) continue;
-        if (!cmp) {
-#pragma unroll
-            for (int c = 0; c < NW; ++c) out[row * 8 + c] = tot[c];
-        } else {
-            for (int v = 0; v < nvec; ++v) {
-                const double e = tot[v] - cmp[row * 8 + v];
-                const double b = cmp[row * 8 + 4 + v];
-                const double ae = e < 0 ? -e : e;
-                const bool ok = ae <= tol * b;
-                double ratio = b > 0 ? ae / b : (ae == 0 ? 0.0 : __builtin_inf());
-                if (ratio != ratio) ratio = __builtin_inf();
-                if (!ok) atomicMax((unsigned long long*)&res->slot[0], (unsigned long long)~(((uint64_t)v << 40) | (uint64_t)row));
-                const uint64_t rb = __builtin_bit_cast(uint64_t, ratio);
-                worst = rb > worst ? rb : worst;
-            }
-        }
-    }
-    if (cmp) {
-        __shared__ uint64_t wmax[4];
-        if (lane == 0) wmax[wave] = worst;
         __syncthreads();
-        if (tid == 0) {
-            uint64_t m = 0;
-            for (int w = 0; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
-            if (m) atomicMax((unsigned long long*)&res->sum[0], (unsigned long long)m);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int jl = 4 * lane + 256 * g;
+            double xv[PC_RPW][4];
+#pragma unroll
+            for (int r = 0; r < PC_RPW; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xv[r][q] = (double)x[g][r][q];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                // columns past the chunk hold zeros in w and in x
+                const double4 wa = *(const double4*)&w[c][jl];
+                const double wq[4] = {wa.x, wa.y, wa.z, wa.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < PC_RPW; ++r) acc[r][c] += (c < 4 ? xv[r][q] : __builtin_fabs(xv[r][q])) * wq[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PC_RPW; ++r) {
+        const int64_t row = row0 + r;
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            const double t = pc_wsum(acc[r][c]);
+            if (lane == 0 && row < rows) part[((int64_t)blockIdx.y * rows + row) * 8 + c] = t;
         }
     }
 }
 
+// out[row][c] = sum over slices s (in order) of part[s][row][c], c < 8
+__global__ __launch_bounds__(256) void pc_combine(const double* __restrict__ part, int64_t slices, int64_t rows,
+                                                  double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= rows * 8) return;
+    double s = 0.0;
+    for (int64_t k = 0; k < slices; ++k) s += part[k * rows * 8 + i];
+    out[i] = s;
+}
+
+// The last pass: C r_v (sum of the slices) against AW; violations and the largest ratio.
+__global__ __launch_bounds__(256) void pc_compare(const double* __restrict__ part, int64_t slices, int64_t rows,
+                                                  const double* __restrict__ AW, int nvec, double tol,
+                                                  InstResult* res) {
+    __shared__ uint64_t wmax[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row = (int64_t)blockIdx.x * 256 + tid;
+    uint64_t worst = 0;
+    if (row < rows) {
+        for (int v = 0; v < nvec; ++v) {
+            double cr = 0.0;
+            for (int64_t k = 0; k < slices; ++k) cr += part[(k * rows + row) * 8 + v];
+            const double e = cr - AW[row * 8 + v];
+            const double b = AW[row * 8 + 4 + v];
+            const double ae = e < 0 ? -e : e;
+            const bool ok = ae <= tol * b;
+            double ratio = b > 0 ? ae / b : (ae == 0 ? 0.0 : __builtin_inf());
+            if (ratio != ratio) ratio = __builtin_inf();
+            if (!ok) atomicMax((unsigned long long*)&res->slot[0], (unsigned long long)~(((uint64_t)v << 40) | (uint64_t)row));
+            const uint64_t rb = __builtin_bit_cast(uint64_t, ratio);
+            worst = rb > worst ? rb : worst;
+        }
+    }
+    // nonnegative doubles order as their bit patterns: one atomic per workgroup
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t y = __shfl_xor(worst, o);
+        worst = y > worst ? y : worst;
+    }
+    if (lane == 0) wmax[wave] = worst;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t m = 0;
+        for (int w = 0; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+        if (m) atomicMax((unsigned long long*)&res->sum[0], (unsigned long long)m);
+    }
+}
+
+// column slices of one pass: enough workgroups to fill the device, slices a multiple of the
+// LDS chunk
+struct PcSplit {
+    int64_t slices, width, row_blocks;
+};
+inline PcSplit pc_split(int64_t rows, int64_t cols) {
+    PcSplit s;
+    s.row_blocks = std::max<int64_t>(1, (rows + PC_RPB - 1) / PC_RPB);
+    const int64_t chunks = std::max<int64_t>(1, (cols + PC_CH - 1) / PC_CH);
+    const int64_t want = std::min<int64_t>(chunks, std::max<int64_t>(1, (PC_TARGET_BLOCKS + s.row_blocks - 1) / s.row_blocks));
+    s.width = ((chunks + want - 1) / want) * PC_CH;
+    s.slices = std::max<int64_t>(1, (cols + s.width - 1) / s.width);
+    return s;
+}
+
 }  // namespace sg
+
+// Workspace (bytes) of a product check with C (M x N) = A (M x K) B (K x N).
+size_t sg_product_check_work_bytes(int64_t M, int64_t N, int64_t K) {
+    using namespace sg;
+    const PcSplit p1 = pc_split(K, N), p2 = pc_split(M, K), p3 = pc_split(M, N);
+    const int64_t part = std::max(p1.slices * K, std::max(p2.slices * M, p3.slices * M));
+    return (size_t)(K * 8 + M * 8 + part * 8) * sizeof(double);
+}
 
 hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
                                    int64_t N, int64_t K, int64_t nvec, double tol, double* work,
                                    sg::InstResult* res, hipStream_t s) {
     using namespace sg;
     if (nvec < 1 || nvec > 4) return hipErrorInvalidValue;
-    double* BW = work;           // K x 8
-    double* AW = work + K * 8;   // M x 8
-    const int rows_per_block = 4 * PRW;
-    auto blocks = [&](int64_t rows) { return (unsigned)((rows + rows_per_block - 1) / rows_per_block > 0 ? (rows + rows_per_block - 1) / rows_per_block : 1); };
-    hipLaunchKernelGGL(rowdot_kernel<8>, dim3(blocks(K)), dim3(256), 0, s, B, K, N, R, (int)nvec, (const double*)nullptr,
-                       BW, (const double*)nullptr, tol, res, 1);
-    hipLaunchKernelGGL(rowdot_kernel<8>, dim3(blocks(M)), dim3(256), 0, s, A, M, K, (const float*)nullptr, (int)nvec,
-                       (const double*)BW, AW, (const double*)nullptr, tol, res, 0);
-    hipLaunchKernelGGL(rowdot_kernel<4>, dim3(blocks(M)), dim3(256), 0, s, C, M, N, R, (int)nvec, (const double*)nullptr,
-                       (double*)nullptr, (const double*)AW, tol, res, 0);
+    double* BW = work;                 // K x 8
+    double* AW = work + K * 8;         // M x 8
+    double* part = work + (K + M) * 8; // slices x rows x 8
+    auto grid1 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)); };
+    const PcSplit p1 = pc_split(K, N), p2 = pc_split(M, K), p3 = pc_split(M, N);
+    hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p1.row_blocks, (unsigned)p1.slices), dim3(256), 0, s, B, K, N, R,
+                       (int)nvec, (const double*)nullptr, p1.width, part, res, 1);
+    hipLaunchKernelGGL(pc_combine, grid1(K * 8), dim3(256), 0, s, (const double*)part, p1.slices, K, BW);
+    hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p2.row_blocks, (unsigned)p2.slices), dim3(256), 0, s, A, M, K,
+                       (const float*)nullptr, (int)nvec, (const double*)BW, p2.width, part, res, 0);
+    hipLaunchKernelGGL(pc_combine, grid1(M * 8), dim3(256), 0, s, (const double*)part, p2.slices, M, AW);
+    hipLaunchKernelGGL(pc_part<4>, dim3((unsigned)p3.row_blocks, (unsigned)p3.slices), dim3(256), 0, s, C, M, N, R,
+                       (int)nvec, (const double*)nullptr, p3.width, part, res, 0);
+    hipLaunchKernelGGL(pc_compare, grid1(M), dim3(256), 0, s, (const double*)part, p3.slices, M, (const double*)AW,
+                       (int)nvec, tol, res);
     return hipGetLastError();
 }
