@@ -117,7 +117,7 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
     // index spaces differ, or the joint pass would exceed the kernel's limits (then the plan
     // is rebuilt without sharing).
     bool hmerge = fused;
-    for (int attempt = 0; attempt < 16; ++attempt) {
+    for (int attempt = 0; attempt < 64; ++attempt) {
         DSU dsu;
         std::map<sg_node_s*, int> vnode;                          // compute vertex of a node
         std::map<std::pair<sg_node_s*, long>, int> vsrc;          // source vertex (node, consumer key)
@@ -290,7 +290,25 @@ sg_status build_plan(sg_program_s* P, Plan* plan) {
                         resplit = true;
                         break;
                     }
-                    if (nspace >= MAX_SPACES) return fail(ctx, SG_E_UNSUPPORTED, "more than 7 filters in one pass; add a split point");
+                    if (nspace >= MAX_SPACES) {
+                        // too many nested filters for one pass: the operands of this and every
+                        // later filter of the pass are written out and read back by a new pass
+                        bool cut_any = false;
+                        bool past = false;
+                        for (auto* f : nodes) {
+                            past |= f == n;
+                            if (!past || f->op != OPN_FILTER) continue;
+                            sg_node_s* o = f->src[0];
+                            if (o && is_elementwise(o) && is_collection(o) && !cut.count(o)) {
+                                mat.insert(o);
+                                cut.insert(o);
+                                cut_any = true;
+                            }
+                        }
+                        if (!cut_any) return fail(ctx, SG_E_UNSUPPORTED, "more than 7 filters in one pass; add a split point");
+                        resplit = true;
+                        break;
+                    }
                     space_filter[nspace] = n;
                     sp[n] = nspace++;
                 } else {
