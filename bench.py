@@ -282,26 +282,41 @@ def run_cfg5(ctx, n_train: int, n_test: int, seed: int = 51) -> dict:
                     for _ in range(2)]}
 
     train_specs = []
+    rejected = []
+    CHUNK = 250  # chains built, timed and released together (each program holds its outputs)
 
-    def programs(count, s0):
+    def timed_chains(count, s0, on_chunk=None):
+        """Build, time and release the seeded chains in chunks; on_chunk(programs, timings)
+        sees every chunk while its programs exist."""
         lengths = W.selector_lengths(count, s0)
-        out = []
-        for i, n in enumerate(lengths):
-            sp = W.selector_chain_spec(int(n), s0 * 100003 + i)
-            if s0 == seed:
-                train_specs.append(sp)
-            dt = sp["inputs"][0]["dtype"]
-            views = {inp["name"]: bufs[dt][k][:inp["n"]] for k, inp in enumerate(sp["inputs"])}
-            out.append(sg.build_spec(ctx, sp, views))
+        out = selector.Timings()
+        for c0 in range(0, count, CHUNK):
+            progs = []
+            for i in range(c0, min(count, c0 + CHUNK)):
+                sp = W.selector_chain_spec(int(lengths[i]), s0 * 100003 + i)
+                if s0 == seed:
+                    train_specs.append(sp)
+                dt = sp["inputs"][0]["dtype"]
+                views = {inp["name"]: bufs[dt][k][:inp["n"]] for k, inp in enumerate(sp["inputs"])}
+                progs.append(sg.build_spec(ctx, sp, views))
+            rej = []
+            t = selector.collect([b.program for b in progs], rejected=rej)
+            rejected.extend((c0 + i, p, msg) for i, p, msg in rej)
+            if on_chunk is not None:
+                on_chunk(progs, t)
+            out.X += t.X
+            out.ms += t.ms
+            out.plans += t.plans
+            del progs
+            if (c0 + CHUNK) % 1000 == 0 or c0 + CHUNK >= count:
+                log(f"cfg5: timed {min(count, c0 + CHUNK)}/{count} chains")
         return out
 
     ctx.set_specialize(False)
     ctx.set_mode("pre_post")
     log(f"cfg5: timing candidate plans of {n_train} training chains")
     t0 = time.perf_counter()
-    train_b = programs(n_train, seed)
-    rejected = []
-    tr = selector.collect([b.program for b in train_b], progress=500, rejected=rejected)
+    tr = timed_chains(n_train, seed)
     for i, p, msg in rejected[:3]:
         log(f"cfg5: plan {p} refused for chain {i} ({msg}): {json.dumps(train_specs[i])}")
     t_collect = time.perf_counter() - t0
@@ -311,16 +326,23 @@ def run_cfg5(ctx, n_train: int, n_test: int, seed: int = 51) -> dict:
     net, losses = selector.train(ctx, tr, W.mlp_init_params(seed), epochs=60)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del train_b
     log(f"cfg5: held-out chains ({n_test})")
-    test_b = programs(n_test, seed + 1)
-    te = selector.collect([b.program for b in test_b], progress=500, rejected=rejected)
-    ev = selector.evaluate(net, [b.program for b in test_b], te)
-    # inference cost of one choice (features + forward of every candidate plan)
-    t0 = time.perf_counter()
-    for b, plans in zip(test_b[:200], te.plans[:200]):
-        net.select(b.program, plans, 0.01)
-    t_infer = (time.perf_counter() - t0) / min(200, len(test_b))
+    choices = []
+    t_infer = [0.0, 0]
+
+    def choose(progs, t):
+        # the model's choice for each held-out chain (features of its candidate plans, then a
+        # forward pass); the first 200 choices are timed
+        for b, plans in zip(progs, t.plans):
+            t1 = time.perf_counter()
+            choices.append(net.select(b.program, plans, 0.01))
+            if t_infer[1] < 200:
+                t_infer[0] += time.perf_counter() - t1
+                t_infer[1] += 1
+
+    te = timed_chains(n_test, seed + 1, on_chunk=choose)
+    ev = selector.evaluate_choices(choices, te)
+    t_infer = t_infer[0] / max(t_infer[1], 1)
     Xt, mst = te.device()
     Xtn, yt = net.standardize(Xt, mst)
     pred = net.predict(Xtn)

@@ -39,18 +39,49 @@ struct JitKernel {
 std::mutex g_mu;
 std::map<std::tuple<int, std::string>, JitKernel*> g_cache;  // (device, source) -> kernel
 
+// A predicate followed by the check that pops it (outside the compacted space, whose checks
+// are resolved after the scan) becomes one CHK_PRED operation.
+std::vector<SgOp> fuse_checks(const InstPlan& ip) {
+    std::vector<SgOp> out;
+    for (size_t i = 0; i < ip.prog.size(); ++i) {
+        const SgOp& p = ip.prog[i];
+        const bool is_pred = p.code == P_FINITE || p.code == P_CMP_F || p.code == P_CMP_I || p.code == P_RANGE_F ||
+                             p.code == P_RANGE_I;
+        if (is_pred && i + 1 < ip.prog.size()) {
+            const SgOp& c = ip.prog[i + 1];
+            if ((c.code == CHK_ALL || c.code == CHK_ANY) && (c.sp == 0 || c.sp != ip.scan_space)) {
+                SgOp f{};
+                f.code = CHK_PRED;
+                f.pad = p.code;
+                f.sp2 = p.code == P_CMP_F || p.code == P_CMP_I ? p.aux : 0;
+                f.a = p.a;
+                f.c0 = p.c0;
+                f.c1 = p.c1;
+                f.dst = c.code == CHK_ALL ? 0 : 1;
+                f.sp = c.sp;
+                f.aux = c.aux;
+                out.push_back(f);
+                ++i;
+                continue;
+            }
+        }
+        out.push_back(p);
+    }
+    return out;
+}
+
 std::string program_source(const InstPlan& ip) {
     std::string s = "// generated: one pass program, operations as constants\n";
     char buf[320];
-    for (const SgOp& o : ip.prog) {
+    for (const SgOp& o : fuse_checks(ip)) {
         uint32_t c0, c1;
         std::memcpy(&c0, &o.c0, 4);
         std::memcpy(&c1, &o.c1, 4);
         std::snprintf(buf, sizeof(buf),
                       "{\n  SgOp op;\n  op.code = %u; op.dst = %u; op.a = %u; op.b = %u; op.sp = %u; op.sp2 = %u; "
-                      "op.aux = %u; op.pad = 0;\n  op.c0.i = (int32_t)0x%08xu; op.c1.i = (int32_t)0x%08xu;\n"
+                      "op.aux = %u; op.pad = %u;\n  op.c0.i = (int32_t)0x%08xu; op.c1.i = (int32_t)0x%08xu;\n"
                       "  const uint8_t code = %u;\n",
-                      o.code, o.dst, o.a, o.b, o.sp, o.sp2, o.aux, c0, c1, o.code);
+                      o.code, o.dst, o.a, o.b, o.sp, o.sp2, o.aux, o.pad, c0, c1, o.code);
         s += buf;
         s += "#include \"sg_stream_ops.inc\"\n}\n";
     }
@@ -58,13 +89,18 @@ std::string program_source(const InstPlan& ip) {
 }
 
 std::string unit_source(const InstPlan& ip, int unroll, int lb) {
-    char buf[512];
+    // sources a sortedness check reads past the end of a wave's part (their next element is
+    // prefetched with the sub-tile; no other source needs it)
+    int nbr = 0;
+    for (const SgOp& o : ip.prog)
+        if (o.code == CHK_SORTED_F || o.code == CHK_SORTED_I) nbr |= 1 << (o.b & 7);
+    char buf[640];
     std::snprintf(buf, sizeof(buf),
                   "#define SG_PROGRAM_INC \"sg_program_gen.inc\"\n#define SG_GEN_HAS_SCAN %d\n#define SG_GEN_NIN %d\n"
-                  "#define SG_GEN_NSLOTS %d\n#define SG_GEN_NSUMS %d\n"
+                  "#define SG_GEN_NSLOTS %d\n#define SG_GEN_NSUMS %d\n#define SG_GEN_NBR_MASK 0x%x\n"
                   "#include \"sg_stream_kernel.h\"\n"
                   "// instantiated through the name expression sg::stream_kernel<%d, true, %d, 1>\n",
-                  ip.scan_space != 0 ? 1 : 0, (int)ip.sources.size(), (int)ip.slot_kind.size(), ip.nsum, unroll, lb);
+                  ip.scan_space != 0 ? 1 : 0, (int)ip.sources.size(), (int)ip.slot_kind.size(), ip.nsum, nbr, unroll, lb);
     return buf;
 }
 

@@ -82,22 +82,55 @@ void* dev_alloc(sg_ctx_s* ctx, size_t bytes) {
     if (it != ctx->pool.end() && !it->second.empty()) {
         void* p = it->second.back();
         it->second.pop_back();
+        ctx->pooled_bytes -= bytes;
         return p;
     }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        return nullptr;
+        // the pool keeps freed blocks by size, so blocks of sizes that do not come back pile up:
+        // return them to the device (after the work that may still use them) and try again
+        if (pool_trim(ctx) == 0 || hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
     }
     ctx->sizes[p] = bytes;
     return p;
 }
+
+size_t pool_trim(sg_ctx_s* ctx) {
+    size_t freed = 0;
+    bool synced = false;
+    for (auto& kv : ctx->pool) {
+        for (void* q : kv.second) {
+            if (!synced) {
+                (void)hipDeviceSynchronize();  // pooled blocks may still be read by queued kernels
+                synced = true;
+            }
+            (void)hipFree(q);
+            ctx->sizes.erase(q);
+            freed += kv.first;
+        }
+        kv.second.clear();
+    }
+    ctx->pool.clear();
+    ctx->pooled_bytes = 0;
+    return freed;
+}
+
+// Pooled blocks beyond this many bytes go back to the device: blocks of sizes that do not
+// come back (programs over many different lengths) would otherwise hold the device memory
+// that later allocations, and the runtime's own, need.
+constexpr size_t kPoolCapBytes = (size_t)16 << 30;
 
 void dev_free(sg_ctx_s* ctx, void* p) {
     if (!p) return;
     auto it = ctx->sizes.find(p);
     if (it == ctx->sizes.end()) return;
     ctx->pool[it->second].push_back(p);
+    ctx->pooled_bytes += it->second;
+    if (ctx->pooled_bytes > kPoolCapBytes) (void)pool_trim(ctx);
 }
 
 // Scratch of the streaming kernel, zeroed once: the kernel leaves the accumulators zero and

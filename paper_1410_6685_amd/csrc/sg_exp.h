@@ -118,6 +118,14 @@ SG_HD float exp_rn_slow(float t) {
     return round_dd_to_f32(res.hi * s, res.lo * s);
 }
 
+// The 29 bits of y below binary32 precision lie within 16 units of the half-way pattern
+// 2^28: low29 in [2^28 - 16, 2^28 + 16].  Shifted left by 3 (the three bits above them drop
+// out) and offset, that is one unsigned comparison: (low29 * 8 - (2^31 - 128)) mod 2^32 <= 256.
+SG_HD bool near_half(double y) {
+    const uint32_t lo = (uint32_t)__builtin_bit_cast(uint64_t, y);
+    return (lo << 3) + (128u - 0x80000000u) <= 256u;
+}
+
 // Fast path: returns RN32(exp t) and hard = false, or hard = true when t needs the
 // double-double path.  `tab` is SG_EXPF_TAB (2^(j/64)); kernels pass a copy in LDS.
 //
@@ -141,9 +149,8 @@ SG_HD float exp_rn_core(float t, const double* tab, bool& hard) {
     q = fma(q, r, 0.5);
     const double p = fma(q, r * r, r);  // exp(r) - 1
     const double T = tab[k & 63];
-    const double y = fma(T, p, T) * pow2d(k >> 6);
-    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, y) & 0x1FFFFFFFu;
-    hard = low - (0x10000000u - 16u) <= 32u;
+    const double y = __builtin_ldexp(fma(T, p, T), k >> 6);  // exact: the result is a normal double
+    hard = near_half(y);
     return (float)y;
 }
 
@@ -166,10 +173,9 @@ SG_HD float exp_rn_fast(float t, const double* tab, bool& hard) {
     const double p = fma(q, r * r, r);  // exp(r) - 1
     const double T = tab[k & 63];
     const double y = fma(T, p, T) * pow2d(k >> 6);
-    const uint32_t low = (uint32_t)__builtin_bit_cast(uint64_t, y) & 0x1FFFFFFFu;
     // exp(t) < 2^-125.5 (t < -87) is near or below the binary32 normal range: slow path
     const bool special = t != t || t >= u2f(SG_EXP_OVF_BITS) || t <= u2f(SG_EXP_UNF_BITS);
-    hard = !special && (t < -87.0f || low - (0x10000000u - 16u) <= 32u);
+    hard = !special && (t < -87.0f || near_half(y));
     float f = (float)y;
     f = t <= u2f(SG_EXP_UNF_BITS) || t < -87.0f ? 0.0f : f;
     f = t >= u2f(SG_EXP_OVF_BITS) ? __builtin_inff() : f;

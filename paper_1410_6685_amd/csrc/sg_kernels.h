@@ -69,6 +69,11 @@ enum OpCode : uint8_t {
     RED_MAX_F, RED_MIN_F, RED_MAX_I, RED_MIN_I,  // -> slot aux
     RED_COUNT,     // number of elements of space sp -> slot aux
     EMIT,          // write register a to output aux (space 0: dense; scan space: compacted)
+    // a predicate and the CHK_ALL / CHK_ANY that pops it, as one operation (formed by the
+    // run-time compiler for checks outside the compacted space): predicate opcode in pad,
+    // its comparison in sp2, register a, constants c0 / c1; dst 0 = for_all, 1 = exists;
+    // space sp, slot aux.  Same result as the pair.
+    CHK_PRED,
     OP_COUNT_
 };
 

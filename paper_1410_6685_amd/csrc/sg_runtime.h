@@ -65,7 +65,8 @@ struct sg_ctx_s {
     uint64_t next_id = 0;
     uint64_t generation = 0;  // bumped when a setting that changes plans changes
     std::string error;
-    std::map<size_t, std::vector<void*>> pool;
+    std::map<size_t, std::vector<void*>> pool;  // freed blocks by size, reused by later allocations
+    size_t pooled_bytes = 0;                     // bytes held in `pool`
     std::unordered_map<void*, size_t> sizes;
     sgrt::Scratch scratch;
     sg::InstResult* host_results = nullptr;
@@ -203,6 +204,8 @@ sg_status check_device_range(sg_ctx_s* ctx, const void* p, size_t bytes, const c
 sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what);
 void* dev_alloc(sg_ctx_s* ctx, size_t bytes);
 void dev_free(sg_ctx_s* ctx, void* p);
+// Return every pooled (freed, unused) block to the device after the device is idle; bytes freed.
+size_t pool_trim(sg_ctx_s* ctx);
 sg_status ensure_scratch(sg_ctx_s* ctx, int64_t tiles, int64_t chunks, int64_t insts);
 sg_status alloc_scratch(sg_ctx_s* ctx, Scratch& S, int64_t tiles, int64_t chunks, int64_t insts);
 uint32_t next_epoch(sg_ctx_s* ctx);

@@ -39,6 +39,9 @@
 #ifndef SG_GEN_NIN
 #define SG_GEN_NIN MAX_IN  // at most this many loaded sources
 #endif
+#ifndef SG_GEN_NBR_MASK
+#define SG_GEN_NBR_MASK 0xF  // sources whose next element a sortedness check reads (bit per source)
+#endif
 
 namespace sg {
 
@@ -114,6 +117,18 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Inclusive sum over the lanes of a wave (lane i gets lanes 0..i): shifts within rows of
+// 16 lanes, then the row broadcasts of lane 15 and lane 31 (data-parallel primitives, no LDS).
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
 }
 
@@ -759,7 +774,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                             for (int v = 0; v < V; ++v) R[k][v] = (inb >> v) & 1u ? q[elem(v)] : 0u;
                         }
                         const int64_t ex = sub_base + (int64_t)(wave + 1) * RW;
-                        nbr[k] = ex < n ? q[ex] : 0u;
+                        nbr[k] = ((SG_GEN_NBR_MASK >> k) & 1) && ex < n ? q[ex] : 0u;
                     }
                 }
 #pragma unroll
@@ -826,7 +841,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                         N[k][4 * u + 2] = w.z;
                         N[k][4 * u + 3] = w.w;
                     }
-                    NX[k] = *(nvec && nex < n ? q + nex : safe);
+                    NX[k] = (SG_GEN_NBR_MASK >> k) & 1 ? *(nvec && nex < n ? q + nex : safe) : 0u;
                 }
             }
 
@@ -836,19 +851,26 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             if (SG_GEN_HAS_SCAN && scan_space != 0) {
                 const uint32_t keep = get_space(S, scan_space);
                 // rank of value v within the region = (kept values of chunks before u)
-                //   + (kept values of lanes below in chunk u) + (kept values j' < j of this lane)
+                //   + (kept values of lanes below in chunk u) + (kept values j' < j of this lane).
+                // Each lane counts its kept values per chunk (16-bit fields, two chunks per
+                // word); one inclusive scan per word over the wave gives the lanes below, and
+                // the last lane's sums are the chunk totals.
+                constexpr int NCW = (U + 1) / 2;
+                uint32_t cw[NCW], iw[NCW];
+#pragma unroll
+                for (int w = 0; w < NCW; ++w) {
+                    const uint32_t lo = (uint32_t)__builtin_popcount((keep >> (8 * w)) & 0xFu);
+                    const uint32_t hi = 2 * w + 1 < U ? (uint32_t)__builtin_popcount((keep >> (8 * w + 4)) & 0xFu) : 0u;
+                    cw[w] = lo | (hi << 16);
+                    iw[w] = wave_incl_add(cw[w]);
+                }
                 uint32_t lbase[U];
                 uint32_t agg = 0;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    uint32_t below = 0, tot = 0;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const uint64_t b = __ballot((keep >> (4 * u + j)) & 1u);
-                        below += __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-                        tot += (uint32_t)__builtin_popcountll(b);
-                    }
-                    lbase[u] = agg + below;
+                    const int w = u >> 1, sh = 16 * (u & 1);
+                    const uint32_t tot = ((uint32_t)__builtin_amdgcn_readlane((int)iw[w], 63) >> sh) & 0xFFFFu;
+                    lbase[u] = agg + (((iw[w] - cw[w]) >> sh) & 0xFFFFu);  // fields never borrow
                     agg += tot;
                 }
                 auto rank_of = [&](int v) -> uint32_t {

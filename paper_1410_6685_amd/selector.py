@@ -106,9 +106,14 @@ class Evaluation:
 def evaluate(net, programs, timings: Timings, margin: float = 0.01) -> Evaluation:
     """Learned choice vs the autotuner (the fastest measured plan) on held-out chains; a
     fallback takes the autotuner's plan."""
+    choices = [net.select(prog, plans, margin) for prog, plans in zip(programs, timings.plans)]
+    return evaluate_choices(choices, timings)
+
+
+def evaluate_choices(choices, timings: Timings) -> Evaluation:
+    """`evaluate` from the model's choices (net.select results, one per chain, in order)."""
     regrets, learned, gains, hits, fb = [], [], [], 0, 0
-    for prog, plans, ms in zip(programs, timings.plans, timings.ms):
-        best, _, fallback = net.select(prog, plans, margin)
+    for (best, _, fallback), plans, ms in zip(choices, timings.plans, timings.ms):
         tuned = int(np.argmin(ms))
         chosen = tuned if fallback else best
         fb += fallback
