@@ -432,6 +432,32 @@ sg_status sg_tunedb_record(sg_tunedb db, uint64_t key, const sg_plan* plan, doub
 sg_status sg_autotune_db(sg_program p, sg_tunedb db, const sg_plan* plans, int32_t n, int32_t reps, int32_t* best,
                          double* ms_out, int32_t* measured);
 
+/* ---- a call that allocates nothing ------------------------------------------------------ */
+
+/* Bytes of static device work memory behind sg_product_check_noalloc (one copy per device,
+ * held until the process ends). */
+#define SG_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * that must not call hipMalloc): the product check of sg_program_product as one call on
+ * device pointers.  C (M x N), A (M x K), B (K x N) and R (nvec x N, 1 <= nvec <= 4) are
+ * row-major float32 matrices in device memory, read only; the check and its tolerance are
+ * those of sg_program_product.  The call enqueues its kernels on `hip_stream` (a hipStream_t of
+ * the current device, NULL = the null stream) and returns without waiting; when the stream
+ * reaches them, *verdict_dev (device memory the caller owns, 32 bytes) holds the verdict as
+ * sg_program_execute would report it (contract_id 0, SG_ENSURE, SG_CHECK_PRODUCT).
+ * Nothing is allocated: the work memory is the static array above, so the call fails with
+ * SG_E_INVALID when 256 + the check's work (8 (K + M) + 8 S max(K, M) doubles, S the column
+ * slices of a pass) exceeds SG_NOALLOC_SCRATCH_BYTES (square matrices up to about 43000), and
+ * calls on one device share that memory: calls that overlap on one device (several streams or
+ * threads) race and must be ordered by the caller.  No device memory is touched before the
+ * arguments are checked.  Errors: SG_E_INVALID (negative size, NULL pointer, too large),
+ * SG_E_UNSUPPORTED (nvec outside 1..4), SG_E_DEVICE (HIP error); no context, so the message is
+ * read with sg_last_error(NULL). */
+sg_status sg_product_check_noalloc(const float* C_dev, const float* A_dev, const float* B_dev, const float* R_dev,
+                                   int64_t M, int64_t N, int64_t K, int32_t nvec, void* hip_stream,
+                                   sg_verdict* verdict_dev);
+
 /* ---- host-side checks of device arithmetic (no GPU needed) ------------------------------ */
 
 /* Evaluate the device code's correctly rounded binary32 exp on the host for n values;

@@ -120,6 +120,7 @@ def _sig(lib):
         "sg_tunedb_lookup": [H, ctypes.c_uint64, H, P(c_double)],
         "sg_tunedb_record": [H, ctypes.c_uint64, H, c_double],
         "sg_autotune_db": [H, H, H, c_int32, c_int32, P(c_int32), P(c_double), P(c_int32)],
+        "sg_product_check_noalloc": [H, H, H, H, c_int64, c_int64, c_int64, c_int32, H, H],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -170,6 +171,33 @@ def host_expr_run(text: str, x, registers: int = 5):
     nops = c_int32()
     _check(load().sg_host_expr_run(text.encode(), registers, x.ctypes.data, out.ctypes.data, x.size, byref(nops)))
     return out, nops.value
+
+
+def _product_check_noalloc_raw(C, A, B, R, M, N, K, nvec, verdict_dev, stream=None):
+    """sg_product_check_noalloc with explicit sizes; the argument checks are the library's."""
+    import torch
+    s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    _check(load().sg_product_check_noalloc(C.data_ptr(), A.data_ptr(), B.data_ptr(), R.data_ptr(), M, N, K, nvec,
+                                           s, verdict_dev.data_ptr()))
+
+
+def product_check_noalloc(C, A, B, R, verdict_dev, stream=None):
+    """The product check of C = A B with the probe rows of R (sg_product_check_noalloc), for
+    callers that cannot allocate: enqueued on `stream` (torch's current stream by default) with
+    no allocation and no wait.  The verdict lands in verdict_dev, a CUDA uint8 tensor of at least
+    32 bytes; after synchronizing, ``Verdict.from_buffer_copy(bytes)`` reads it."""
+    import torch
+    for name, t in (("C", C), ("A", A), ("B", B), ("R", R)):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 2):
+            raise ValueError(f"{name}: expected a contiguous 2-D float32 CUDA tensor")
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N) or R.shape[1] != N:
+        raise ValueError(f"shapes disagree: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}, R {tuple(R.shape)}")
+    if not (verdict_dev.is_cuda and verdict_dev.dtype == torch.uint8 and verdict_dev.is_contiguous()
+            and verdict_dev.numel() >= ctypes.sizeof(Verdict) and verdict_dev.data_ptr() % 8 == 0):
+        raise ValueError("verdict_dev: expected a contiguous, 8-byte aligned CUDA uint8 tensor of at least 32 bytes")
+    _product_check_noalloc_raw(C, A, B, R, M, N, K, R.shape[0], verdict_dev, stream)
 
 
 # ---------------------------------------------------------------------------------------------
