@@ -233,17 +233,20 @@ def run_cfg4(ctx, count: int, steps: int, warmup: int) -> dict:
         return e0.elapsed_time(e1) / k
 
     tuned = []
-    for block, unroll in [(256, 1), (256, 2), (256, 4), (512, 2), (1024, 1)]:
+    for block, unroll, subs in [(256, 1, 1), (256, 2, 1), (256, 4, 1), (512, 2, 1), (1024, 1, 1),
+                                (256, 2, 4), (256, 4, 2), (256, 4, 4), (512, 2, 4), (256, 2, 8)]:
         ctx.set_launch(block, unroll)
+        ctx.set_batch_substeps(subs)
         b = sg.Batch(ctx, progs, use_graph=True)
-        tuned.append((time_batch(b, 3), block, unroll))
+        tuned.append((time_batch(b, 3), block, unroll, subs))
         del b
     tuned.sort()
-    _, block, unroll = tuned[0]
+    _, block, unroll, subs = tuned[0]
     ctx.set_launch(block, unroll)
+    ctx.set_batch_substeps(subs)
     batch = sg.Batch(ctx, progs, use_graph=True)
     statuses, _ = batch.run()
-    log(f"cfg4: timing {steps} graph launches (block {block}, unroll {unroll})")
+    log(f"cfg4: timing {steps} graph launches (block {block}, unroll {unroll}, sub-tiles {subs})")
     ms_batch = time_batch(batch, max(steps, 3))
     log("cfg4: timing per-instance launches")
     for p in progs[:50]:
@@ -255,11 +258,13 @@ def run_cfg4(ctx, count: int, steps: int, warmup: int) -> dict:
     torch.cuda.synchronize()
     ms_single = (time.perf_counter() - t0) * 1e3
     ctx.set_launch(256, 2)
+    ctx.set_batch_substeps(1)
     return {"instances": count, "elements": nelem, "algorithmic_bytes": nbytes,
             "batched_graph_ms": round(ms_batch, 4), "batched_GBs": round(nbytes / ms_batch / 1e6, 2),
             "per_instance_ms": round(ms_single, 3), "per_instance_GBs": round(nbytes / ms_single / 1e6, 2),
-            "speedup": round(ms_single / ms_batch, 2), "autotuned_launch": {"block": block, "unroll": unroll},
-            "autotune_candidates_ms": [[b, u, round(t, 4)] for t, b, u in tuned],
+            "speedup": round(ms_single / ms_batch, 2),
+            "autotuned_launch": {"block": block, "unroll": unroll, "substeps": subs},
+            "autotune_candidates_ms": [[b, u, c, round(t, 4)] for t, b, u, c in tuned],
             "violated_instances": int(sum(st != "ok" for st in statuses))}
 
 

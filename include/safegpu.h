@@ -89,6 +89,19 @@ typedef struct sg_verdict {
 enum { SG_CHECK_FOR_ALL = 0, SG_CHECK_EXISTS = 1, SG_CHECK_SORTED = 2, SG_CHECK_CLOSE = 3,
        SG_CHECK_PRODUCT = 4, SG_CHECK_COUNT_EQ = 5, SG_CHECK_QUOTIENT = 6 };
 
+/* Device memory for the library's outputs and work buffers from the caller's allocator (for
+ * example the framework's caching allocator, so that one pool serves both).  alloc returns
+ * `bytes` of device memory usable by work on `stream` (the context's hipStream_t) or NULL;
+ * free releases it; the library calls free only after enqueueing the last work that uses
+ * the block on that stream, so a stream-ordered allocator may reuse it at once.  `user` is
+ * passed through.  Stream scratch, batch tables and the static no-alloc array stay the
+ * library's own. */
+typedef struct sg_allocator {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* p, void* stream, void* user);
+    void* user;
+} sg_allocator;
+
 /* ---- context ---------------------------------------------------------------------------- */
 
 /* Create a context on HIP device `device` (Section 2.2: the runtime that owns device memory
@@ -98,6 +111,10 @@ enum { SG_CHECK_FOR_ALL = 0, SG_CHECK_EXISTS = 1, SG_CHECK_SORTED = 2, SG_CHECK_
 sg_status sg_ctx_create(int device, void* hip_stream, sg_ctx* out);
 /* Releases the context once every node, program and batch made from it is released. */
 sg_status sg_ctx_destroy(sg_ctx ctx);
+/* Use `a` (copied; both functions non-NULL) for the device memory allocated from now on, or the
+ * library's own pool when a is NULL.  Blocks keep the allocator they came from.  SG_E_INVALID
+ * for a NULL context or a half-filled allocator. */
+sg_status sg_ctx_set_allocator(sg_ctx ctx, const sg_allocator* a);
 /* Contract monitoring mode (Section 6.3: no checking, preconditions only, pre- and
  * postconditions).  SG_E_INVALID for an unknown mode. */
 sg_status sg_ctx_set_mode(sg_ctx ctx, sg_mode mode);
@@ -109,6 +126,11 @@ sg_status sg_ctx_set_fusion(sg_ctx ctx, int fused);
  * Section 5): block size (64..1024, multiple of 64) and unroll (1, 2 or 4: 16-byte loads per
  * lane per input and sub-tile).  0 keeps the default; other values give SG_E_INVALID. */
 sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll);
+/* Sub-tiles per tile (1..16) of the batched launches created afterwards (sg_batch_create):
+ * a tile is the unit a block takes, publishes and finalizes, so larger tiles mean fewer such
+ * steps per element; capped where the tile's compaction staging would not fit in LDS.
+ * Default 1.  SG_E_INVALID outside 1..16. */
+sg_status sg_ctx_set_batch_substeps(sg_ctx ctx, int substeps);
 /* on != 0: run every single-program pass through a kernel compiled at run time (hiprtc) for
  * that pass's program, as the paper generates one kernel per merged plan (Section 5);
  * compiled once per device and program, then cached for the process.  on == 0 (default):

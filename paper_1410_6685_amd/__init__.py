@@ -60,6 +60,18 @@ class Verdict(ctypes.Structure):
                 f"{CHECKS.get(self.check)}, holds={self.holds}, first={self.first_index}, measure={self.measure:g})")
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+
+_KEEP_ALLOCATORS = []
+
+
+class Allocator(ctypes.Structure):
+    """sg_allocator: device memory from the caller (alloc(bytes, stream, user), free(p, stream, user))."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", c_void_p)]
+
+
 class SafeGPUError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -74,6 +86,7 @@ def _sig(lib):
         "sg_ctx_create": [c_int, H, P(H)], "sg_ctx_destroy": [H], "sg_ctx_set_mode": [H, c_int],
         "sg_ctx_set_fusion": [H, c_int], "sg_ctx_set_launch": [H, c_int, c_int], "sg_ctx_set_timing": [H, c_int],
         "sg_ctx_set_specialize": [H, c_int], "sg_ctx_set_wait_limit": [H, c_int64],
+        "sg_ctx_set_batch_substeps": [H, c_int], "sg_ctx_set_allocator": [H, H],
         "sg_ctx_last_launch": [H, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int64)],
         "sg_ctx_timing": [H, c_char_p, P(c_double), P(c_int64)], "sg_ctx_timing_reset": [H],
         "sg_vector_wrap": [H, c_int, H, c_int64, P(H)], "sg_matrix_wrap": [H, c_int, H, c_int64, c_int64, P(H)],
@@ -760,6 +773,33 @@ class Context:
 
     def set_launch(self, block: int = 0, unroll: int = 0):
         _check(load().sg_ctx_set_launch(self.h, block, unroll), self.h)
+
+    def set_batch_substeps(self, substeps: int):
+        _check(load().sg_ctx_set_batch_substeps(self.h, substeps), self.h)
+
+    def use_torch_allocator(self, on: bool = True):
+        """Outputs and work buffers from torch's caching allocator (sg_ctx_set_allocator), so the
+        library and torch share one pool; on=False returns to the library's own pool."""
+        if not on:
+            _check(load().sg_ctx_set_allocator(self.h, None), self.h)
+            return
+        import torch
+        dev = self.device
+
+        def _alloc(nbytes, stream, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=stream or 0)
+            except Exception:  # out of memory: the library reports SG_E_OOM
+                return None
+
+        def _free(p, stream, user):
+            torch.cuda.caching_allocator_delete(p)
+
+        # the callbacks must outlive every block allocated through them, which may be released
+        # after this object (nodes keep the library's context alive): kept for the process
+        self._allocator = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+        _KEEP_ALLOCATORS.append(self._allocator)
+        _check(load().sg_ctx_set_allocator(self.h, byref(self._allocator)), self.h)
 
     def set_specialize(self, on: bool):
         _check(load().sg_ctx_set_specialize(self.h, int(on)), self.h)

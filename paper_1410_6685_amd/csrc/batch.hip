@@ -61,7 +61,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     ctx_retain(ctx);
     b->block = ctx->block;
     b->unroll = ctx->unroll;
-    b->substeps = 1;  // one sub-tile per tile: instances are small next to the grid
+    b->substeps = 1;  // sub-tiles per tile: the context's batch setting, as far as LDS allows
     std::vector<InstDesc> descs;
     std::vector<SgOp> ops;
     std::vector<int32_t> tile_inst;
@@ -88,6 +88,8 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
     }
     // the per-lane accumulators and staging buffers of every instance must fit in LDS
     for (;; b->unroll /= 2) {
+        b->substeps = stream_substeps(ctx->batch_substeps, b->block, b->unroll, max_slots, max_sums, max_cemit,
+                                      any_scan, 1);
         b->lds = stream_lds_bytes(max_slots, max_sums, max_cemit, b->substeps, b->block, b->unroll, 1);
         if (b->lds <= kMaxDynamicLds || b->unroll == 1) break;
     }
@@ -95,7 +97,7 @@ sg_status sg_batch_create(sg_ctx ctx, const sg_program* progs, int32_t n, int us
         batch_free(b);
         return fail(ctx, SG_E_UNSUPPORTED, "batch needs more LDS than a block has; use a smaller block");
     }
-    const int64_t tile_elems = (int64_t)b->block * 4 * b->unroll;
+    const int64_t tile_elems = (int64_t)b->block * 4 * b->unroll * b->substeps;
     for (int i = 0; i < n; ++i) {
         InstPlan& ip = b->progs[i]->plan.insts[0];
         const int64_t nt = std::max<int64_t>(1, (ip.n + tile_elems - 1) / tile_elems);

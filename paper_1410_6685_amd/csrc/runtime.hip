@@ -78,6 +78,11 @@ sg_status check_device_range(sg_ctx_s* ctx, const void* p, size_t bytes, const c
 void* dev_alloc(sg_ctx_s* ctx, size_t bytes) {
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
+    if (ctx->ext.alloc) {  // the caller's allocator
+        void* p = ctx->ext.alloc(bytes, (void*)ctx->stream, ctx->ext.user);
+        if (p) ctx->ext_blocks[p] = ctx->ext;
+        return p;
+    }
     auto it = ctx->pool.find(bytes);
     if (it != ctx->pool.end() && !it->second.empty()) {
         void* p = it->second.back();
@@ -126,6 +131,13 @@ constexpr size_t kPoolCapBytes = (size_t)16 << 30;
 
 void dev_free(sg_ctx_s* ctx, void* p) {
     if (!p) return;
+    auto xe = ctx->ext_blocks.find(p);
+    if (xe != ctx->ext_blocks.end()) {  // back to the allocator it came from
+        const sg_allocator a = xe->second;
+        ctx->ext_blocks.erase(xe);
+        a.free(p, (void*)ctx->stream, a.user);
+        return;
+    }
     auto it = ctx->sizes.find(p);
     if (it == ctx->sizes.end()) return;
     ctx->pool[it->second].push_back(p);
@@ -201,6 +213,8 @@ void ctx_release(sg_ctx_s* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->pool)
         for (void* p : kv.second) (void)hipFree(p);
+    // blocks from a caller's allocator are all back by now: every node, program and batch that
+    // held one has released the context before this point
     if (ctx->scratch.base) (void)hipFree(ctx->scratch.base);
     if (ctx->host_results) (void)hipHostFree(ctx->host_results);
     for (auto& ev : ctx->events) (void)hipEventDestroy(ev);
@@ -410,6 +424,17 @@ sg_status sg_ctx_destroy(sg_ctx ctx) {
     return SG_OK;
 }
 
+sg_status sg_ctx_set_allocator(sg_ctx ctx, const sg_allocator* a) {
+    if (!ctx) return SG_E_INVALID;
+    if (!a) {
+        ctx->ext = sg_allocator{};
+        return SG_OK;
+    }
+    if (!a->alloc || !a->free) return fail(ctx, SG_E_INVALID, "set_allocator: alloc and free are both needed");
+    ctx->ext = *a;
+    return SG_OK;
+}
+
 sg_status sg_ctx_set_mode(sg_ctx ctx, sg_mode mode) {
     if (!ctx || mode < SG_MODE_OFF || mode > SG_MODE_PRE_POST) return fail(ctx, SG_E_INVALID, "bad mode");
     ctx->mode = mode;
@@ -430,6 +455,13 @@ sg_status sg_ctx_set_launch(sg_ctx ctx, int block, int unroll) {
     if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4) return fail(ctx, SG_E_INVALID, "unroll must be 1, 2 or 4");
     if (block) ctx->block = block;
     if (unroll) ctx->unroll = unroll;
+    return SG_OK;
+}
+
+sg_status sg_ctx_set_batch_substeps(sg_ctx ctx, int substeps) {
+    if (!ctx) return SG_E_INVALID;
+    if (substeps < 1 || substeps > 16) return fail(ctx, SG_E_INVALID, "batch sub-tiles per tile must be 1..16");
+    ctx->batch_substeps = substeps;
     return SG_OK;
 }
 

@@ -137,21 +137,38 @@ SG_HD bool near_half(double y) {
 // 16 units of the half-way pattern 2^28.  Results below the binary32 normal range take the
 // slow path (their rounding position differs).
 // The float64 core alone, for an ordinary argument: -87 <= t < the overflow threshold.
-SG_HD float exp_rn_core(float t, const double* tab, bool& hard) {
-    const double td = (double)t;
-    const double sh = fma(td, SG_EXPF_INV_L, 0x1.8p52);
-    const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, sh);
-    const double kd = sh - 0x1.8p52;
-    double r = fma(-kd, SG_EXPF_L1, td);
+SG_HD float exp_rn_core(float t, const double* tab, bool& hard);
+
+// The core in two stages, so that a caller can issue the table reads of several elements before
+// it evaluates their polynomials: the reduction gives the table index (k mod 64) and the
+// rounded multiple; the finish combines the table entry with exp(r) - 1.
+struct ExpCore {
+    double td, sh;
+    int idx;
+};
+SG_HD ExpCore exp_core_reduce(float t) {
+    ExpCore c;
+    c.td = (double)t;
+    c.sh = fma(c.td, SG_EXPF_INV_L, 0x1.8p52);
+    c.idx = (int)(uint32_t)__builtin_bit_cast(uint64_t, c.sh) & 63;
+    return c;
+}
+SG_HD float exp_core_finish(const ExpCore& c, double T, bool& hard) {
+    const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, c.sh);
+    const double kd = c.sh - 0x1.8p52;
+    double r = fma(-kd, SG_EXPF_L1, c.td);
     r = fma(-kd, SG_EXPF_L2, r);
     double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
     q = fma(q, r, 1.0 / 6.0);
     q = fma(q, r, 0.5);
     const double p = fma(q, r * r, r);  // exp(r) - 1
-    const double T = tab[k & 63];
     const double y = __builtin_ldexp(fma(T, p, T), k >> 6);  // exact: the result is a normal double
     hard = near_half(y);
     return (float)y;
+}
+SG_HD float exp_rn_core(float t, const double* tab, bool& hard) {
+    const ExpCore c = exp_core_reduce(t);
+    return exp_core_finish(c, tab[c.idx], hard);
 }
 
 // an argument the core handles (NaN fails both comparisons)

@@ -57,6 +57,7 @@ struct sg_ctx_s {
     int block = 256;
     int unroll = 2;
     int substeps = 8;
+    int batch_substeps = 1;  // sub-tiles per tile of batched launches
     uint32_t epoch = 0;  // host epoch of direct launches
     int last_grid = 0, last_block = 0, last_unroll = 0, last_substeps = 0;  // last streaming launch
     size_t last_lds = 0;
@@ -68,6 +69,8 @@ struct sg_ctx_s {
     std::map<size_t, std::vector<void*>> pool;  // freed blocks by size, reused by later allocations
     size_t pooled_bytes = 0;                     // bytes held in `pool`
     std::unordered_map<void*, size_t> sizes;
+    sg_allocator ext{};                          // the caller's allocator (alloc null: none)
+    std::unordered_map<void*, sg_allocator> ext_blocks;  // blocks from a caller's allocator
     sgrt::Scratch scratch;
     sg::InstResult* host_results = nullptr;
     std::map<std::string, sgrt::KTime> times;

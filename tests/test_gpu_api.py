@@ -186,3 +186,46 @@ def test_batch_recovers_after_forced_wait_failure(sg, ctx):
         statuses, verdicts = batch.run()
         for i, (sp, x, b) in enumerate(zip(specs, inputs, builts)):
             compare(sp, b, statuses[i], verdicts[i:i + 1], oracle.evaluate(sp, x))
+
+
+def test_outputs_from_torch_caching_allocator(sg):
+    """With the caller's allocator (torch's caching allocator through sg_ctx_set_allocator) the
+    library's outputs and work buffers come from torch's pool: the results equal the oracle's,
+    torch's allocated bytes grow by at least the compacted output while the program lives, and
+    fall back once it is released."""
+    import gc
+
+    import torch
+    c = sg.Context(0)
+    c.use_torch_allocator()
+    n = 300_007
+    spec, inp = W.cfg2_spec(n), W.cfg2_inputs(n)
+    tens = to_dev(inp)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    built = sg.build_spec(c, spec, tens)
+    status, verdicts = built.program.execute()
+    torch.cuda.synchronize()
+    during = torch.cuda.memory_allocated()
+    assert during - before >= 4 * n  # the compacted output (capacity n float32) is torch's
+    compare(spec, built, status, verdicts, oracle.evaluate(spec, inp))
+    # a matrix product's check work buffer and a quicksort's buffers come from torch as well
+    g = np.random.default_rng(3)
+    A = g.integers(-4, 5, size=(130, 70)).astype(np.float32)
+    B = g.integers(-4, 5, size=(70, 90)).astype(np.float32)
+    mspec = {"inputs": [{"name": "A", "dtype": "f32", "rows": 130, "cols": 70},
+                        {"name": "B", "dtype": "f32", "rows": 70, "cols": 90},
+                        {"name": "R", "dtype": "f32", "rows": 2, "cols": 90}],
+             "nodes": [{"name": "C", "op": "matmul", "a": "A", "b": "B"}],
+             "contracts": [{"kind": "ensure", "check": "product", "node": "C", "a": "A", "b": "B", "r": "R"}],
+             "outputs": ["C"]}
+    minp = {"A": A, "B": B, "R": g.integers(-3, 4, size=(2, 90)).astype(np.float32)}
+    mb = sg.build_spec(c, mspec, to_dev(minp))
+    st, vs = mb.program.execute()
+    assert st == "ok" and vs[0].holds == 1
+    assert np.array_equal(mb["C"].to_host().reshape(130, 90), (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32))
+    del built, mb
+    gc.collect()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before + 4096
+    c.use_torch_allocator(False)

@@ -60,14 +60,16 @@ def test_batch_matches_oracle_and_single(sg, ctx, use_graph):
 def test_batch_with_launch_configs(sg, ctx):
     specs, inputs = make_instances(60, 11, 8.0, 17.0)
     builts = [sg.build_spec(ctx, sp, to_dev(inp)) for sp, inp in zip(specs, inputs)]
-    for block, unroll in [(64, 1), (256, 2), (1024, 4)]:
-        say("batch launch", block, unroll)
+    for block, unroll, subs in [(64, 1, 1), (256, 2, 1), (1024, 4, 1), (256, 4, 4), (256, 2, 16), (512, 2, 3)]:
+        say("batch launch", block, unroll, subs)
         ctx.set_launch(block, unroll)
+        ctx.set_batch_substeps(subs)
         try:
             batch = sg.Batch(ctx, [b.program for b in builts], use_graph=True)
             statuses, verdicts = batch.run()
         finally:
             ctx.set_launch(256, 2)
+            ctx.set_batch_substeps(1)
         k = 0
         for i, (sp, inp, b) in enumerate(zip(specs, inputs, builts)):
             nv = len(sp["contracts"])
