@@ -5,10 +5,13 @@
 // a-priori rounding bound of a K-term float32 dot product (doubled because the matrix
 // cores' summation order is unspecified) plus slack for this float64 evaluation.  The
 // reported index is the first violating row of the first probe that has one, and the measure
-// is max |e_i| / b_i.  Three streaming passes read B, A and C once each:
-//   1. BW = [B r_v | |B| |r_v|]          (K x 8)
+// is max |e_i| / b_i.  After RW = [r_v | |r_v|] (N x 8, float64) is written, three streaming
+// passes read B, A and C once each:
+//   1. BW = [B RW_v | |B| RW_(4+v)]       (K x 8)
 //   2. AW = [A BW_v | |A| BW_(4+v)]       (M x 8)
-//   3. C r_v, compared row by row with AW.
+//   3. C RW_v, compared row by row with AW.
+// RW and BW are padded with zero rows to a whole number of LDS chunks, so a pass loads its
+// right-hand side with no bounds conditions.
 // Each pass is a row-by-matrix product with a narrow right-hand side.  The columns are split
 // into slices so that a 4096-row pass still has thousands of workgroups: a workgroup stages
 // its slice of the right-hand side in LDS (float64, 512 columns at a time), each of its four
@@ -29,39 +32,49 @@ constexpr int PC_RPB = 4 * PC_RPW;        // rows per workgroup (4 waves)
 constexpr int PC_CH = 512;                // columns staged in LDS at a time
 constexpr int PC_TARGET_BLOCKS = 2048;    // workgroups a pass aims for
 
-__device__ __forceinline__ double pc_wsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+// rows of a padded right-hand side: cols rounded up to a whole number of LDS chunks
+__host__ __device__ inline int64_t pc_pad(int64_t cols) { return (cols + PC_CH - 1) / PC_CH * PC_CH; }
 
-// part[slice][row][c] = sum over the slice's columns j of f_c(X[row][j]) W[j][c], with
-// f_c(x) = x for c < 4 and |x| for c >= 4.  W[j] is [r_0..r_3, |r_0|..|r_3|][j] taken from R
-// (nvec x cols floats; missing probes are zero) when Wd is null, else row j of the cols x 8
-// float64 matrix Wd.  NW = 4 computes the first four columns only.
-template <int NW>
-__global__ __launch_bounds__(256) void pc_part(const float* __restrict__ X, int64_t rows, int64_t cols,
-                                               const float* __restrict__ R, int nvec,
-                                               const double* __restrict__ Wd, int64_t slice_w,
-                                               double* __restrict__ part, InstResult* res, int zero_res) {
-    __shared__ __align__(16) double w[NW][PC_CH];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (zero_res && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+// RW[j] = [r_0..r_3, |r_0|..|r_3|][j] for j < cols (missing probes zero), zero rows up to
+// pc_pad(cols); also clears the verdict the passes accumulate into.
+__global__ __launch_bounds__(256) void pc_prep(const float* __restrict__ R, int nvec, int64_t cols,
+                                               double* __restrict__ RW, InstResult* res) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j == 0) {
         res->slot[0] = 0;
         res->sum[0] = 0.0;
         res->err = 0;
     }
-    const int64_t row0 = (int64_t)blockIdx.x * PC_RPB + wave * PC_RPW;
-    const int64_t s0 = (int64_t)blockIdx.y * slice_w, s1 = std::min<int64_t>(cols, s0 + slice_w);
-    const bool vec = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0);
-    double acc[PC_RPW][NW];
+    if (j >= pc_pad(cols)) return;
+    double r[4];
 #pragma unroll
-    for (int r = 0; r < PC_RPW; ++r)
-#pragma unroll
-        for (int c = 0; c < NW; ++c) acc[r][c] = 0.0;
+    for (int v = 0; v < 4; ++v) r[v] = (j < cols && v < nvec) ? (double)R[(int64_t)v * cols + j] : 0.0;
+    double4* o = (double4*)(RW + j * 8);
+    o[0] = make_double4(r[0], r[1], r[2], r[3]);
+    o[1] = make_double4(__builtin_fabs(r[0]), __builtin_fabs(r[1]), __builtin_fabs(r[2]), __builtin_fabs(r[3]));
+}
 
+// One wave's sums over the columns [s0, s1) of its PC_RPW rows from row0, chunk by chunk: acc[r][c] +=
+// f_c(X[row0 + r][j]) W[j][c].  FULL: every row and every chunk of the range lies inside the
+// matrix and X rows are 16-byte aligned, so the loads take no condition (a divergent branch
+// around each load would make every load wait for the one before it).
+template <int NW, bool FULL>
+__device__ __forceinline__ void pc_chunks(const float* __restrict__ X, int64_t rows, int64_t cols,
+                                          const double* __restrict__ Wd, int64_t s0, int64_t s1, int64_t row0,
+                                          double (&acc)[PC_RPW][NW], double (&w)[NW][PC_CH]) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    static_assert(PC_CH == 512, "two right-hand side rows per thread, two float4 per row and lane");
     for (int64_t c0 = s0; c0 < s1; c0 += PC_CH) {
-        const int cw = (int)std::min<int64_t>(PC_CH, s1 - c0);
+        const int cw = FULL ? PC_CH : (int)std::min<int64_t>(PC_CH, s1 - c0);
+        // this thread's rows of the right-hand side (j = tid, tid + 256), issued before the
+        // rows of X so that both are in flight together; the padding makes them all present
+        double4 wa[2], wb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double* wp = Wd + (c0 + tid + 256 * h) * 8;
+            wa[h] = *(const double4*)wp;
+            if (NW == 8) wb[h] = *(const double4*)(wp + 4);
+        }
         // this chunk's rows of X: columns c0 + 4 lane + 256 g (+0..3), g = 0, 1
         float x[2][PC_RPW][4];
 #pragma unroll
@@ -69,35 +82,24 @@ __global__ __launch_bounds__(256) void pc_part(const float* __restrict__ X, int6
             const int jl = 4 * lane + 256 * g;
 #pragma unroll
             for (int r = 0; r < PC_RPW; ++r) {
-                const int64_t row = row0 + r;
-                const float* xp = X + row * cols + c0 + jl;
-                if (row < rows && vec && jl + 3 < cw) {
+                const float* xp = X + (row0 + r) * cols + c0 + jl;
+                if (FULL) {
                     const float4 v = *(const float4*)xp;
                     x[g][r][0] = v.x; x[g][r][1] = v.y; x[g][r][2] = v.z; x[g][r][3] = v.w;
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) x[g][r][q] = (row < rows && jl + q < cw) ? xp[q] : 0.f;
+                    for (int q = 0; q < 4; ++q) x[g][r][q] = (row0 + r < rows && jl + q < cw) ? xp[q] : 0.f;
                 }
             }
         }
         __syncthreads();  // the previous chunk's right-hand side is no longer read
         // stored transposed (w[c][j]): a lane's four consecutive columns are one contiguous
         // 32-byte run, and a wave's reads of one c cover 2 KiB contiguously (no bank conflicts)
-        for (int j = tid; j < PC_CH; j += 256) {
-            if (j >= cw) {
 #pragma unroll
-                for (int c = 0; c < NW; ++c) w[c][j] = 0.0;
-            } else if (Wd) {
-#pragma unroll
-                for (int c = 0; c < NW; ++c) w[c][j] = Wd[(c0 + j) * 8 + c];
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float rv = v < nvec ? R[(int64_t)v * cols + c0 + j] : 0.f;
-                    w[v][j] = (double)rv;
-                    if (NW == 8) w[(v + 4) % NW][j] = (double)__builtin_fabsf(rv);
-                }
-            }
+        for (int h = 0; h < 2; ++h) {
+            const int j = tid + 256 * h;
+            w[0][j] = wa[h].x; w[1][j] = wa[h].y; w[2][j] = wa[h].z; w[3][j] = wa[h].w;
+            if (NW == 8) { w[4 % NW][j] = wb[h].x; w[5 % NW][j] = wb[h].y; w[6 % NW][j] = wb[h].z; w[7 % NW][j] = wb[h].w; }
         }
         __syncthreads();
 #pragma unroll
@@ -110,9 +112,9 @@ __global__ __launch_bounds__(256) void pc_part(const float* __restrict__ X, int6
                 for (int q = 0; q < 4; ++q) xv[r][q] = (double)x[g][r][q];
 #pragma unroll
             for (int c = 0; c < NW; ++c) {
-                // columns past the chunk hold zeros in w and in x
-                const double4 wa = *(const double4*)&w[c][jl];
-                const double wq[4] = {wa.x, wa.y, wa.z, wa.w};
+                // columns past the matrix hold zeros in w (padding) and in x
+                const double4 wv = *(const double4*)&w[c][jl];
+                const double wq[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -120,24 +122,73 @@ __global__ __launch_bounds__(256) void pc_part(const float* __restrict__ X, int6
             }
         }
     }
+}
+
+// part[slice][row][c] = sum over the slice's columns j of f_c(X[row][j]) W[j][c], with
+// f_c(x) = x for c < 4 and |x| for c >= 4, W a padded float64 right-hand side with 8 columns
+// (pc_pad(cols) rows, 32-byte aligned).  NW = 4 computes the first four columns only.
+template <int NW>
+__global__ __launch_bounds__(256, 3) void pc_part(const float* __restrict__ X, int64_t rows, int64_t cols,
+                                               const double* __restrict__ Wd, int64_t slice_w,
+                                               double* __restrict__ part) {
+    __shared__ __align__(16) double w[NW][PC_CH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * PC_RPB + wave * PC_RPW;
+    const int64_t s0 = (int64_t)blockIdx.y * slice_w, s1 = std::min<int64_t>(cols, s0 + slice_w);
+    double acc[PC_RPW][NW];
 #pragma unroll
-    for (int r = 0; r < PC_RPW; ++r) {
-        const int64_t row = row0 + r;
+    for (int r = 0; r < PC_RPW; ++r)
 #pragma unroll
-        for (int c = 0; c < NW; ++c) {
-            const double t = pc_wsum(acc[r][c]);
-            if (lane == 0 && row < rows) part[((int64_t)blockIdx.y * rows + row) * 8 + c] = t;
+        for (int c = 0; c < NW; ++c) acc[r][c] = 0.0;
+    // the same for the whole workgroup (it depends on the block indices only)
+    const bool full = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((int64_t)blockIdx.x + 1) * PC_RPB <= rows &&
+                      (s1 - s0) % PC_CH == 0;
+    if (full)
+        pc_chunks<NW, true>(X, rows, cols, Wd, s0, s1, row0, acc, w);
+    else
+        pc_chunks<NW, false>(X, rows, cols, Wd, s0, s1, row0, acc, w);
+    // Sums over the wave of the PC_RPW x NW per-lane values by halving: at each step a lane
+    // keeps half of its values and adds its partner's matching half, so after log2(NV) steps
+    // lane l holds one value whole or in part, and the remaining steps add across the lanes
+    // that share it.  32 exchanges instead of one six-step butterfly per value.
+    constexpr int NV = PC_RPW * NW;
+    double v[NV];
+#pragma unroll
+    for (int r = 0; r < PC_RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < NW; ++c) v[r * NW + c] = acc[r][c];
+    int idx = 0;  // index of the first value this lane still holds
+#pragma unroll
+    for (int m = NV, o = 32; m > 1; m >>= 1, o >>= 1) {
+        const bool upper = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < m / 2; ++i) {
+            const double mine = upper ? v[m / 2 + i] : v[i];
+            const double other = upper ? v[i] : v[m / 2 + i];
+            v[i] = mine + __shfl_xor(other, o);
         }
+        idx += upper ? m / 2 : 0;
+    }
+    // lanes that hold the same value (they differ only in the offsets below 64 / NV) add up
+    static_assert(NV == 16 || NV == 32, "values per lane");
+#pragma unroll
+    for (int o = 64 / NV / 2; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
+    if ((lane & (64 / NV - 1)) == 0) {
+        const int r = idx / NW, c = idx % NW;
+        const int64_t row = row0 + r;
+        if (row < rows) part[((int64_t)blockIdx.y * rows + row) * 8 + c] = v[0];
     }
 }
 
-// out[row][c] = sum over slices s (in order) of part[s][row][c], c < 8
+// out[row][c] = sum over slices s (in order) of part[s][row][c], c < 8, for row < rows; zero
+// rows after that up to out_rows
 __global__ __launch_bounds__(256) void pc_combine(const double* __restrict__ part, int64_t slices, int64_t rows,
-                                                  double* __restrict__ out) {
+                                                  int64_t out_rows, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= rows * 8) return;
+    if (i >= out_rows * 8) return;
     double s = 0.0;
-    for (int64_t k = 0; k < slices; ++k) s += part[k * rows * 8 + i];
+    if (i < rows * 8)
+        for (int64_t k = 0; k < slices; ++k) s += part[k * rows * 8 + i];
     out[i] = s;
 }
 
@@ -201,7 +252,7 @@ size_t sg_product_check_work_bytes(int64_t M, int64_t N, int64_t K) {
     using namespace sg;
     const PcSplit p1 = pc_split(K, N), p2 = pc_split(M, K), p3 = pc_split(M, N);
     const int64_t part = std::max(p1.slices * K, std::max(p2.slices * M, p3.slices * M));
-    return (size_t)(K * 8 + M * 8 + part * 8) * sizeof(double);
+    return (size_t)(pc_pad(N) * 8 + pc_pad(K) * 8 + M * 8 + part * 8) * sizeof(double);
 }
 
 hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
@@ -209,19 +260,23 @@ hipError_t sg_launch_product_check(const float* C, const float* A, const float* 
                                    sg::InstResult* res, hipStream_t s) {
     using namespace sg;
     if (nvec < 1 || nvec > 4) return hipErrorInvalidValue;
-    double* BW = work;                 // K x 8
-    double* AW = work + K * 8;         // M x 8
-    double* part = work + (K + M) * 8; // slices x rows x 8
+    if ((uintptr_t)work % 32 != 0) return hipErrorInvalidValue;
+    double* RW = work;                      // pc_pad(N) x 8
+    double* BW = RW + pc_pad(N) * 8;        // pc_pad(K) x 8
+    double* AW = BW + pc_pad(K) * 8;        // M x 8
+    double* part = AW + M * 8;              // slices x rows x 8
     auto grid1 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)); };
     const PcSplit p1 = pc_split(K, N), p2 = pc_split(M, K), p3 = pc_split(M, N);
-    hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p1.row_blocks, (unsigned)p1.slices), dim3(256), 0, s, B, K, N, R,
-                       (int)nvec, (const double*)nullptr, p1.width, part, res, 1);
-    hipLaunchKernelGGL(pc_combine, grid1(K * 8), dim3(256), 0, s, (const double*)part, p1.slices, K, BW);
+    hipLaunchKernelGGL(pc_prep, grid1(pc_pad(N)), dim3(256), 0, s, R, (int)nvec, N, RW, res);
+    hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p1.row_blocks, (unsigned)p1.slices), dim3(256), 0, s, B, K, N,
+                       (const double*)RW, p1.width, part);
+    hipLaunchKernelGGL(pc_combine, grid1(pc_pad(K) * 8), dim3(256), 0, s, (const double*)part, p1.slices, K,
+                       pc_pad(K), BW);
     hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p2.row_blocks, (unsigned)p2.slices), dim3(256), 0, s, A, M, K,
-                       (const float*)nullptr, (int)nvec, (const double*)BW, p2.width, part, res, 0);
-    hipLaunchKernelGGL(pc_combine, grid1(M * 8), dim3(256), 0, s, (const double*)part, p2.slices, M, AW);
-    hipLaunchKernelGGL(pc_part<4>, dim3((unsigned)p3.row_blocks, (unsigned)p3.slices), dim3(256), 0, s, C, M, N, R,
-                       (int)nvec, (const double*)nullptr, p3.width, part, res, 0);
+                       (const double*)BW, p2.width, part);
+    hipLaunchKernelGGL(pc_combine, grid1(M * 8), dim3(256), 0, s, (const double*)part, p2.slices, M, M, AW);
+    hipLaunchKernelGGL(pc_part<4>, dim3((unsigned)p3.row_blocks, (unsigned)p3.slices), dim3(256), 0, s, C, M, N,
+                       (const double*)RW, p3.width, part);
     hipLaunchKernelGGL(pc_compare, grid1(M), dim3(256), 0, s, (const double*)part, p3.slices, M, (const double*)AW,
                        (int)nvec, tol, res);
     return hipGetLastError();
