@@ -234,7 +234,8 @@ def run_cfg4(ctx, count: int, steps: int, warmup: int) -> dict:
 
     tuned = []
     for block, unroll, subs in [(256, 1, 1), (256, 2, 1), (256, 4, 1), (512, 2, 1), (1024, 1, 1),
-                                (256, 2, 4), (256, 4, 2), (256, 4, 4), (512, 2, 4), (256, 2, 8)]:
+                                (256, 2, 4), (256, 4, 2), (256, 4, 4), (512, 2, 4), (256, 2, 8), (256, 4, 8),
+                                (256, 4, 16), (512, 4, 4)]:
         ctx.set_launch(block, unroll)
         ctx.set_batch_substeps(subs)
         b = sg.Batch(ctx, progs, use_graph=True)

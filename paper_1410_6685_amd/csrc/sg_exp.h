@@ -6,11 +6,12 @@
 // a different element count.
 //
 // Method (table-driven reduction after Tang, ACM TOMS 15(2), 1989, evaluated in float64):
-//   k = rint(t * 64/ln2), r = t - k*ln2/64 (|r| <= ln2/128), j = k mod 64, m = floor(k/64),
-//   exp(t) = 2^m * 2^(j/64) * exp(r),  exp(r) - 1 by its degree-5 Taylor polynomial.
-// The float64 result y has relative error below 2^-51.  If y lies clearly away from every
+//   k = rint(t * 256/ln2), r = t - k*ln2/256 (|r| <= ln2/512), j = k mod 256,
+//   m = floor(k/256), exp(t) = 2^m * 2^(j/256) * exp(r),  exp(r) - 1 by its degree-3
+//   Taylor polynomial (a larger table buys two fewer polynomial steps per element).
+// The float64 result y has relative error below 1.44e-13.  If y lies clearly away from every
 // binary32 rounding boundary (checked on its low mantissa bits), RN32(y) = RN32(exp t).
-// Otherwise (about one element in 2^23) the value is recomputed in double-double arithmetic
+// Otherwise (about one element in 2^17) the value is recomputed in double-double arithmetic
 // (about 2^-100 relative error; 32 intervals, Taylor series to degree 13), which settles
 // the rounding since exp of a nonzero binary32 is never a rounding boundary.
 #pragma once
@@ -118,29 +119,33 @@ SG_HD float exp_rn_slow(float t) {
     return round_dd_to_f32(res.hi * s, res.lo * s);
 }
 
-// The 29 bits of y below binary32 precision lie within 16 units of the half-way pattern
-// 2^28: low29 in [2^28 - 16, 2^28 + 16].  Shifted left by 3 (the three bits above them drop
-// out) and offset, that is one unsigned comparison: (low29 * 8 - (2^31 - 128)) mod 2^32 <= 256.
+// The 29 bits of y below binary32 precision lie within 2048 units of the half-way pattern
+// 2^28: low29 in [2^28 - 2048, 2^28 + 2048].  Shifted left by 3 (the three bits above them
+// drop out) and offset, that is one unsigned comparison:
+// (low29 * 8 - (2^31 - 16384)) mod 2^32 <= 32768.
 SG_HD bool near_half(double y) {
     const uint32_t lo = (uint32_t)__builtin_bit_cast(uint64_t, y);
-    return (lo << 3) + (128u - 0x80000000u) <= 256u;
+    return (lo << 3) + (16384u - 0x80000000u) <= 32768u;
 }
 
 // Fast path: returns RN32(exp t) and hard = false, or hard = true when t needs the
-// double-double path.  `tab` is SG_EXPF_TAB (2^(j/64)); kernels pass a copy in LDS.
+// double-double path.  `tab` is SG_EXPF_TAB (2^(j/256)); kernels pass a copy in LDS.
 //
 // k is rounded to an integer by adding 1.5*2^52 (its low 32 bits are then k in two's
-// complement), r = t - k*ln2/64 is exact up to the F2 term (|r| <= ln2/128 + 2^-40), and
-// exp(r) - 1 is its degree-5 Taylor polynomial (truncation below 2^-54.5).  The float64
-// result y is then within 2^-51 relative of exp(t), i.e. within 4 units of its last
-// place, so RN32(y) = RN32(exp t) unless the 29 bits below binary32 precision lie within
-// 16 units of the half-way pattern 2^28.  Results below the binary32 normal range take the
-// slow path (their rounding position differs).
+// complement), r = t - k*ln2/256 is exact up to the F2 term (|r| <= ln2/512 + 2^-40 <
+// 1.36e-3), and exp(r) - 1 is its degree-3 Taylor polynomial, whose truncation is below
+// r^4/24 * 1.001 < 1.44e-13.  With the float64 roundings of r, the polynomial, the table
+// entry and the product (each 2^-53 relative), the result y is within 1.44e-13 relative of
+// exp(t), i.e. within 2^10.4 < 1300 units of its last place (y < 2^(e+1) for y in
+// [2^e, 2^(e+1))), so RN32(y) = RN32(exp t) unless the 29 bits below binary32 precision
+// lie within 2048 units of the half-way pattern 2^28 (about one argument in 2^17).
+// Results below the binary32 normal range take the slow path (their rounding position
+// differs).
 // The float64 core alone, for an ordinary argument: -87 <= t < the overflow threshold.
 SG_HD float exp_rn_core(float t, const double* tab, bool& hard);
 
 // The core in two stages, so that a caller can issue the table reads of several elements before
-// it evaluates their polynomials: the reduction gives the table index (k mod 64) and the
+// it evaluates their polynomials: the reduction gives the table index (k mod 256) and the
 // rounded multiple; the finish combines the table entry with exp(r) - 1.
 struct ExpCore {
     double td, sh;
@@ -150,7 +155,7 @@ SG_HD ExpCore exp_core_reduce(float t) {
     ExpCore c;
     c.td = (double)t;
     c.sh = fma(c.td, SG_EXPF_INV_L, 0x1.8p52);
-    c.idx = (int)(uint32_t)__builtin_bit_cast(uint64_t, c.sh) & 63;
+    c.idx = (int)(uint32_t)__builtin_bit_cast(uint64_t, c.sh) & ((1 << SG_EXPF_BITS) - 1);
     return c;
 }
 SG_HD float exp_core_finish(const ExpCore& c, double T, bool& hard) {
@@ -158,11 +163,9 @@ SG_HD float exp_core_finish(const ExpCore& c, double T, bool& hard) {
     const double kd = c.sh - 0x1.8p52;
     double r = fma(-kd, SG_EXPF_L1, c.td);
     r = fma(-kd, SG_EXPF_L2, r);
-    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    q = fma(q, r, 1.0 / 6.0);
-    q = fma(q, r, 0.5);
+    const double q = fma(r, 1.0 / 6.0, 0.5);
     const double p = fma(q, r * r, r);  // exp(r) - 1
-    const double y = __builtin_ldexp(fma(T, p, T), k >> 6);  // exact: the result is a normal double
+    const double y = __builtin_ldexp(fma(T, p, T), k >> SG_EXPF_BITS);  // exact: the result is a normal double
     hard = near_half(y);
     return (float)y;
 }
@@ -184,12 +187,10 @@ SG_HD float exp_rn_fast(float t, const double* tab, bool& hard) {
     const double kd = sh - 0x1.8p52;
     double r = fma(-kd, SG_EXPF_L1, td);
     r = fma(-kd, SG_EXPF_L2, r);
-    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    q = fma(q, r, 1.0 / 6.0);
-    q = fma(q, r, 0.5);
+    const double q = fma(r, 1.0 / 6.0, 0.5);
     const double p = fma(q, r * r, r);  // exp(r) - 1
-    const double T = tab[k & 63];
-    const double y = fma(T, p, T) * pow2d(k >> 6);
+    const double T = tab[k & ((1 << SG_EXPF_BITS) - 1)];
+    const double y = fma(T, p, T) * pow2d(k >> SG_EXPF_BITS);
     // exp(t) < 2^-125.5 (t < -87) is near or below the binary32 normal range: slow path
     const bool special = t != t || t >= u2f(SG_EXP_OVF_BITS) || t <= u2f(SG_EXP_UNF_BITS);
     hard = !special && (t < -87.0f || near_half(y));

@@ -234,7 +234,7 @@ size_t stream_lds_bytes(int slots, int sums, int cemit, int C, int block, int un
 int lds_blocks_per_cu(size_t dyn_lds);
 constexpr size_t kLdsPerCu = 160 * 1024;      // LDS of a gfx950 CU
 constexpr size_t kLdsReserve = 2 * 1024;      // margin kept free when sizing a resident grid
-constexpr size_t kStaticLdsBound = 8 * 1024;  // the streaming kernel's static LDS (checked there)
+constexpr size_t kStaticLdsBound = 10 * 1024;  // the streaming kernel's static LDS (checked there)
 // dynamic LDS a streaming block may use (160 KiB per CU, less the kernel's static part)
 constexpr size_t kMaxDynamicLds = 152 * 1024;
 void retain(sg_node_s* n);

@@ -47,14 +47,19 @@ namespace sg {
 
 // ---- small helpers -------------------------------------------------------------------------
 
+// a register-set index as a type (selects one of two copies of the sub-tile code)
+template <int P>
+struct SgPhase {
+    static constexpr int value = P;
+};
+
 __device__ __forceinline__ float uf(uint32_t u) { return __builtin_bit_cast(float, u); }
 __device__ __forceinline__ uint32_t fu(float f) { return __builtin_bit_cast(uint32_t, f); }
 __device__ __forceinline__ int32_t ui(uint32_t u) { return (int32_t)u; }
 
-// order-preserving int32 key of a binary32 value (-0 < +0); NaN handled by the caller
 // all ones when bit v of m is set, else zero
 __device__ __forceinline__ uint32_t lane_mask_bit(uint32_t m, int v) {
-    return (uint32_t)((int32_t)(m << (31 - v)) >> 31);
+    return (uint32_t)__builtin_amdgcn_sbfe((int)m, v, 1);  // one signed bit-field extract
 }
 
 __device__ __forceinline__ bool cmp_f(uint8_t op, float x, float c) {
@@ -249,7 +254,7 @@ __device__ __forceinline__ uint8_t d8_lane(kptr kb, const char* gb, int off) {  
 }
 
 struct Lds {
-    double exptab[64];                       // 2^(j/64) for the exp fast path
+    double exptab[1 << SG_EXPF_BITS];        // 2^(j/256) for the exp fast path
     uint64_t slot[MAX_WAVES][MAX_SLOTS];     // per-wave combines of the per-lane accumulators
     double sum[MAX_WAVES][MAX_SUMS];         // per-wave sums of the current tile
     double tsum[TILE_BUF][MAX_SUMS];         // sums of tiles not yet published
@@ -262,7 +267,7 @@ struct Lds {
     int64_t excl;                            // exclusive prefix of the tile being copied out
 };
 
-static_assert(sizeof(Lds) <= 8 * 1024, "static LDS bound assumed by the host's grid sizing");
+static_assert(sizeof(Lds) <= 10 * 1024, "static LDS bound assumed by the host's grid sizing");
 
 __device__ __forceinline__ uint64_t tag_word(uint32_t epoch, uint32_t payload) {
     return ((uint64_t)epoch << 32) | payload;
@@ -412,7 +417,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
 
     for (int k = 0; k < A.lds_slots; ++k) lacc[k * B + tid] = 0;
     for (int k = 0; k < A.lds_sums; ++k) lsum[k * B + tid] = 0.0;
-    if (tid < 64) L.exptab[tid] = SG_EXPF_TAB[tid];
+    for (int i = tid; i < (1 << SG_EXPF_BITS); i += blockDim.x) L.exptab[i] = SG_EXPF_TAB[i];
     lds_barrier();
 
     // Combine the block's exact accumulators of instance `cur`, publish its buffered tiles;
@@ -654,7 +659,16 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 gu32* q = gout(d64<INLINE>(kdesc, D, (int)__builtin_offsetof(InstDesc, out) + 8 * (ci == 0 ? ce_out0 : ce_out1)));
                 const uint32_t* st = sbase + ((int64_t)ci * C * nwaves + rg) * RW;
                 gu32* dst = q + ob;  // one base per region, 32-bit offsets per store
-                for (uint32_t i = lane; i < cnt; i += 64) dst[i] = st[i];
+                // four reads in flight before their stores (i0 + 255 < RW: the unguarded
+                // reads stay inside the region)
+                for (uint32_t i0 = 0; i0 < cnt; i0 += 256) {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) w[k] = st[i0 + 64 * k + lane];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (i0 + 64 * k + lane < cnt) dst[i0 + 64 * k + lane] = w[k];
+                }
             }
             for (int ci = 0; ci < nd; ++ci) {
                 const uint32_t f = L.dfirst[buf][ci][rg];
@@ -671,13 +685,15 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
         }
     };
 
-    uint32_t R[NREG][V];
-    // Inputs of the block's next sub-tile.  The interpreter loads them into R once the
-    // program is done with R; a specialized kernel (few registers in use) loads them into N
-    // before the program runs, so they are in flight for the whole sub-tile.
+    // Inputs of the block's next sub-tile.  The interpreter loads them into its registers R
+    // once the program is done with R; a specialized kernel (few registers in use) loads them
+    // before the program runs, so they are in flight for the whole sub-tile, into N: the other
+    // of two register sets that alternate from sub-tile to sub-tile (a sub-tile whose inputs
+    // were prefetched runs on the set that received them, so nothing is copied).
     constexpr bool EARLY = SPEC == 1;
     constexpr int NB = EARLY && SG_GEN_NIN > 1 ? (SG_GEN_NIN < MAX_IN ? SG_GEN_NIN : MAX_IN) : 1;
-    uint32_t N[NB][V];
+    uint32_t RB[EARLY ? 2 : 1][NREG][V];
+    int ph = 0;  // specialized kernel: the register set of the sub-tile about to run
     // first element after each wave's part of a sub-tile (the sortedness check's neighbour
     // of the wave's last element), loaded with the part itself
     uint32_t NX[NB], nbr[NB];
@@ -719,7 +735,11 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
             cend = rem <= 0 ? 1 : (int)((rem + sub_elems - 1) / sub_elems < C ? (rem + sub_elems - 1) / sub_elems : C);
         }
 
-        for (int c = 0; c < cend; ++c) {
+        auto subtile = [&](auto phase, const int c) {
+            constexpr int P = decltype(phase)::value;
+            uint32_t(&R)[NREG][V] = RB[P];
+            uint32_t(&N)[NREG][V] = RB[EARLY ? 1 - P : 0];
+            (void)N;
             const int64_t sub_base = (local * C + c) * sub_elems;
             const bool full = sub_base + sub_elems <= n;
             const bool vec = full && (flags & 1);
@@ -751,11 +771,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 // now; all of them have arrived before the next prefetch is issued
                 if (pf) {
 #pragma unroll
-                    for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) {
-                        nbr[k] = NX[k];
-#pragma unroll
-                        for (int v = 0; v < V; ++v) R[k][v] = N[k][v];
-                    }
+                    for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) nbr[k] = NX[k];
                 } else {
 #pragma unroll
                     for (int k = 0; k < NB && k < SG_GEN_NIN; ++k) {
@@ -881,13 +897,21 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                 const int region = c * nwaves + wave;
                 for (int ci = 0; ci < nce; ++ci) {
                     uint32_t* st = stage + sb * stage_buf + ((int64_t)ci * C * nwaves + region) * RW;
-                    // kept values fill the region from the front in element order, the others
-                    // from the back (a region has one slot per element), so every lane writes
-                    // without a branch and no two writes meet; only the front is copied out
-                    SG_ON_REG(ci == 0 ? ce_reg0 : ce_reg1, _Pragma("unroll") for (int v = 0; v < V; ++v) {
-                        const uint32_t rk = rank_of(v);
-                        const uint32_t back = (uint32_t)(RW - 1 - ((v >> 2) * 256 + (v & 3)) - lane * 4) + rk;
-                        st[(keep >> v) & 1u ? rk : back] = r[v];
+                    // kept values fill the region from the front in element order.  Within a
+                    // chunk a lane's kept values are consecutive from lbase[u], so a pointer
+                    // advanced by each element's keep bit addresses them, and a store runs
+                    // only in the lanes whose element is kept (an execution mask, no branch):
+                    // per element one bit extract, one compare and one add.
+                    SG_ON_REG(ci == 0 ? ce_reg0 : ce_reg1, _Pragma("unroll") for (int u = 0; u < U; ++u) {
+                        uint32_t* p = st + lbase[u];
+                        _Pragma("unroll") for (int j = 0; j < 4; ++j) {
+                            // the extracted bit is both the mask's source and the increment
+                            // (through the empty asm the compiler does not test the bit apart)
+                            uint32_t b = (keep >> (4 * u + j)) & 1u;
+                            asm volatile("" : "+v"(b));
+                            if (b) *p = r[4 * u + j];
+                            if (j < 3) p += b;
+                        }
                     })
                 }
                 for (int ci = 0; ci < nd; ++ci) {
@@ -920,6 +944,15 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
                         }
                     }
                 }
+            }
+        };
+        for (int c = 0; c < cend; ++c) {
+            if constexpr (EARLY) {
+                if (ph) subtile(SgPhase<1>{}, c);
+                else subtile(SgPhase<0>{}, c);
+                if (pf) ph ^= 1;  // the next sub-tile's inputs are in the other set
+            } else {
+                subtile(SgPhase<0>{}, c);
             }
         }
 
