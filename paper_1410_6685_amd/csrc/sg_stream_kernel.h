@@ -321,7 +321,7 @@ __global__ __launch_bounds__(LB, LB <= 256 ? 2 : 1) void stream_kernel(const Str
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform over the wave, and visibly so
     const int B = blockDim.x;
     const int nwaves = B >> 6;
     const int C = A.substeps;
