@@ -471,7 +471,7 @@ sg_status sg_autotune_db(sg_program p, sg_tunedb db, const sg_plan* plans, int32
  * Nothing is allocated: the work memory is the static array above, so the call fails with
  * SG_E_INVALID when 256 + the check's work (8 (N' + K' + M) + 8 S max(K, M) doubles, N' and K'
  * rounded up to multiples of 512, S the column slices of a pass) exceeds
- * SG_NOALLOC_SCRATCH_BYTES (every square size up to 26112 fits), and
+ * SG_NOALLOC_SCRATCH_BYTES (every square size up to 32766 fits), and
  * calls on one device share that memory: calls that overlap on one device (several streams or
  * threads) race and must be ordered by the caller.  No device memory is touched before the
  * arguments are checked.  Errors: SG_E_INVALID (negative size, NULL pointer, too large),

@@ -30,7 +30,7 @@ namespace sg {
 constexpr int PC_RPW = 4;                 // rows per wave
 constexpr int PC_RPB = 4 * PC_RPW;        // rows per workgroup (4 waves)
 constexpr int PC_CH = 512;                // columns staged in LDS at a time
-constexpr int PC_TARGET_BLOCKS = 2048;    // workgroups a pass aims for
+constexpr int PC_TARGET_BLOCKS = 512;     // workgroups a pass aims for (two per CU)
 
 // rows of a padded right-hand side: cols rounded up to a whole number of LDS chunks
 __host__ __device__ inline int64_t pc_pad(int64_t cols) { return (cols + PC_CH - 1) / PC_CH * PC_CH; }
@@ -124,14 +124,91 @@ __device__ __forceinline__ void pc_chunks(const float* __restrict__ X, int64_t r
     }
 }
 
+// The same sums for a workgroup whose rows and chunks all lie inside the matrix, software
+// pipelined: the next chunk's right-hand side rows and X rows are loaded while the current
+// chunk is computed, and its right-hand side is staged in the other of two LDS buffers, so a
+// chunk costs one barrier and the loads of one chunk are always in flight.  The loads are
+// unconditional (the last chunk loads itself again, from the caches) so that nothing waits
+// for them before the compute that follows.
+template <int NW>
+__device__ __forceinline__ void pc_chunks_pipe(const float* __restrict__ X, int64_t cols,
+                                               const double* __restrict__ Wd, int64_t s0, int64_t s1, int64_t row0,
+                                               double (&acc)[PC_RPW][NW], double (&w2)[2][NW][PC_CH]) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    double4 wa[2], wb[2];
+    float x[2][PC_RPW][4];
+    auto load = [&](int64_t c0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double* wp = Wd + (c0 + tid + 256 * h) * 8;
+            wa[h] = *(const double4*)wp;
+            if (NW == 8) wb[h] = *(const double4*)(wp + 4);
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int r = 0; r < PC_RPW; ++r) {
+                const float4 v = *(const float4*)(X + (row0 + r) * cols + c0 + 4 * lane + 256 * g);
+                x[g][r][0] = v.x; x[g][r][1] = v.y; x[g][r][2] = v.z; x[g][r][3] = v.w;
+            }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = tid + 256 * h;
+            w2[buf][0][j] = wa[h].x; w2[buf][1][j] = wa[h].y; w2[buf][2][j] = wa[h].z; w2[buf][3][j] = wa[h].w;
+            if (NW == 8) {
+                w2[buf][4 % NW][j] = wb[h].x; w2[buf][5 % NW][j] = wb[h].y;
+                w2[buf][6 % NW][j] = wb[h].z; w2[buf][7 % NW][j] = wb[h].w;
+            }
+        }
+    };
+    load(s0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t c0 = s0; c0 < s1; c0 += PC_CH) {
+        float xc[2][PC_RPW][4];
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int r = 0; r < PC_RPW; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xc[g][r][q] = x[g][r][q];
+        load(c0 + PC_CH < s1 ? c0 + PC_CH : c0);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int jl = 4 * lane + 256 * g;
+            double xv[PC_RPW][4];
+#pragma unroll
+            for (int r = 0; r < PC_RPW; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xv[r][q] = (double)xc[g][r][q];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const double4 wv = *(const double4*)&w2[buf][c][jl];
+                const double wq[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < PC_RPW; ++r) acc[r][c] += (c < 4 ? xv[r][q] : __builtin_fabs(xv[r][q])) * wq[q];
+            }
+        }
+        // the other buffer was last read before the previous barrier
+        stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
 // part[slice][row][c] = sum over the slice's columns j of f_c(X[row][j]) W[j][c], with
 // f_c(x) = x for c < 4 and |x| for c >= 4, W a padded float64 right-hand side with 8 columns
 // (pc_pad(cols) rows, 32-byte aligned).  NW = 4 computes the first four columns only.
 template <int NW>
-__global__ __launch_bounds__(256, 3) void pc_part(const float* __restrict__ X, int64_t rows, int64_t cols,
+__global__ __launch_bounds__(256, 2) void pc_part(const float* __restrict__ X, int64_t rows, int64_t cols,
                                                const double* __restrict__ Wd, int64_t slice_w,
                                                double* __restrict__ part) {
-    __shared__ __align__(16) double w[NW][PC_CH];
+    __shared__ __align__(16) double w2[2][NW][PC_CH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * PC_RPB + wave * PC_RPW;
     const int64_t s0 = (int64_t)blockIdx.y * slice_w, s1 = std::min<int64_t>(cols, s0 + slice_w);
@@ -144,9 +221,9 @@ __global__ __launch_bounds__(256, 3) void pc_part(const float* __restrict__ X, i
     const bool full = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((int64_t)blockIdx.x + 1) * PC_RPB <= rows &&
                       (s1 - s0) % PC_CH == 0;
     if (full)
-        pc_chunks<NW, true>(X, rows, cols, Wd, s0, s1, row0, acc, w);
+        pc_chunks_pipe<NW>(X, cols, Wd, s0, s1, row0, acc, w2);
     else
-        pc_chunks<NW, false>(X, rows, cols, Wd, s0, s1, row0, acc, w);
+        pc_chunks<NW, false>(X, rows, cols, Wd, s0, s1, row0, acc, w2[0]);
     // Sums over the wave of the PC_RPW x NW per-lane values by halving: at each step a lane
     // keeps half of its values and adds its partner's matching half, so after log2(NV) steps
     // lane l holds one value whole or in part, and the remaining steps add across the lanes
