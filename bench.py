@@ -269,6 +269,95 @@ def run_cfg4(ctx, count: int, steps: int, warmup: int) -> dict:
             "violated_instances": int(sum(st != "ok" for st in statuses))}
 
 
+# ---- the paper's other workloads: quicksort, transpose, Gaussian elimination, specialization ------
+
+def _wall_ms(fn, steps: int, warmup: int) -> float:
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def run_next(ctx, steps: int, plan=(256, 4, 2, -1)) -> dict:
+    """Synchronous wall time per execution (inputs resident, contracts pre_post) at the largest
+    sizes the paper plots: quicksort of 10^8 float32 items with 'ensure sorted' and
+    'ensure count = old count'; transpose of a 10^4 x 10^4 matrix (materialized); the
+    determinant of a 1000 x 1000 matrix by Gaussian elimination; the cfg2 pass on the run-time
+    specialized kernel vs the precompiled interpreter (kernel time)."""
+    import torch
+
+    import paper_1410_6685_amd as sg
+    import workloads as W
+
+    ctx.set_mode("pre_post")
+    out = {}
+    k = max(3, steps // 3)
+
+    n = 10 ** 8
+    x = torch.from_numpy(W.normal_f32(n, 61)).cuda()
+    spec = {"inputs": [{"name": "a", "dtype": "f32", "n": n}],
+            "nodes": [{"name": "r", "op": "qsort", "src": "a"}],
+            "contracts": [{"kind": "ensure", "check": "sorted", "node": "r"},
+                          {"kind": "ensure", "check": "count_eq", "node": "r", "other": "a"}],
+            "outputs": ["r"]}
+    built = sg.build_spec(ctx, spec, {"a": x})
+    st = {}
+    ms = _wall_ms(lambda: st.__setitem__("s", built.program.execute()), k, 1)
+    out["quicksort_1e8"] = {"ms": round(ms, 3), "Mitems_per_s": round(n / ms / 1e3, 1), "status": st["s"][0]}
+    del built, x
+    torch.cuda.empty_cache()
+
+    r = c = 10 ** 4
+    M = torch.from_numpy(W.normal_f32(r * c, 62).reshape(r, c)).cuda()
+    spec = {"inputs": [{"name": "M", "dtype": "f32", "rows": r, "cols": c}],
+            "nodes": [{"name": "T", "op": "transpose", "src": "M"}],
+            "contracts": [{"kind": "ensure", "check": "for_all", "node": "T", "pred": ["isfinite"]}],
+            "outputs": ["T"]}
+    built = sg.build_spec(ctx, spec, {"M": M})
+    ms = _wall_ms(lambda: st.__setitem__("s", built.program.execute()), max(k, 10), 2)
+    out["transpose_1e4x1e4"] = {"ms": round(ms, 4), "GBs": round(8.0 * r * c / ms / 1e6, 1), "status": st["s"][0]}
+    del built, M
+    torch.cuda.empty_cache()
+
+    nn = 1000
+    A = torch.from_numpy(W.normal_f32(nn * nn, 63).reshape(nn, nn)).cuda()
+    d = ctx.wrap(A).gauss_det()
+    p = sg.Program(ctx)
+    p.add_root(d)
+    ms = _wall_ms(lambda: p.execute(), max(k, 10), 2)
+    out["gauss_det_1000"] = {"ms": round(ms, 4), "det_parts": list(d.det_parts())}
+    del p, d, A
+
+    nq = N_DEFAULT
+    inp = W.cfg2_inputs(nq)
+    dev = {kk: torch.from_numpy(v).cuda() for kk, v in inp.items()}
+    built = sg.build_spec(ctx, W.cfg2_spec(nq), dev)
+    built.program.set_plan(plan)
+    times = {}
+    for spec_on in (True, False):
+        ctx.set_specialize(spec_on)
+        for _ in range(2):
+            built.program.execute()
+        ctx.set_timing(True)
+        ctx.timing_reset()
+        for _ in range(k):
+            built.program.execute()
+        ctx.set_timing(False)
+        kms, kn = ctx.timing("stream_spec" if spec_on else "stream")
+        times[spec_on] = kms / max(kn, 1)
+    ctx.set_specialize(True)
+    out["cfg2_specialized_vs_interpreter"] = {"plan": list(plan), "specialized_kernel_ms": round(times[True], 4),
+                                              "interpreter_kernel_ms": round(times[False], 4),
+                                              "speedup": round(times[False] / times[True], 3)}
+    return out
+
+
 # ---- learned plan selector ------------------------------------------------------------------------
 
 def run_cfg5(ctx, n_train: int, n_test: int, seed: int = 51) -> dict:
@@ -379,6 +468,8 @@ def main():
     ap.add_argument("--sync", action="store_true", help="synchronous steps (execute) instead of launch/wait pipelining")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 256 MiB device copy (profiling aid)")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the matrix-product workload")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the quicksort / transpose / Gaussian elimination / specialization timings")
     ap.add_argument("--cfg4-instances", type=int, default=10_000, help="0 skips the batched workload")
     ap.add_argument("--cfg5-train", type=int, default=4200,
                     help="training chains, about 12 candidate plans each: ~50k timings (0 skips the selector)")
@@ -505,6 +596,10 @@ def main():
         extras["cfg3_matmul"] = run_cfg3(ctx, max(3, args.steps // 2), 2)
         log("cfg1: plain vs fused chain, n = 2^20")
         extras["cfg1_fusion"] = run_cfg1(ctx, max(20, args.steps), 5)
+        torch.cuda.empty_cache()
+    if not args.no_extras and not args.no_next:
+        log("quicksort, transpose, Gaussian elimination, specialized vs interpreted pass")
+        extras["next_workloads"] = run_next(ctx, args.steps)
         torch.cuda.empty_cache()
     if not args.no_extras and args.cfg4_instances > 0:
         ctx.set_specialize(False)

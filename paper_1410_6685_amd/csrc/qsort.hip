@@ -14,9 +14,11 @@
 //
 // Large segments are partitioned by three kernels per level over 4096-item tiles: count the
 // four classes per tile, scan the tile counts per segment, then scatter (LDS-staged, so that
-// the writes of a tile are four contiguous runs).  Segments of at most 4096 items are finished
-// by one workgroup each in LDS, with the same pivot rule and stable three-way partition, all of
-// the segment's sub-collections partitioned together in each round.
+// the writes of a tile are four contiguous runs).  Segments of at most 2048 items are finished
+// by one workgroup each in LDS: without NaN the recursion's result is the stable sort of the
+// segment, which a bitonic network over (key, position) pairs computes; a segment holding a
+// NaN runs the recursion itself, with the same pivot rule and stable three-way partition, all
+// of the segment's sub-collections partitioned together in each round.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -188,9 +190,19 @@ __global__ __launch_bounds__(QB) void q_scatter(const uint32_t* __restrict__ cur
     }
 }
 
-// ---- leaf kernel: one segment of at most 4096 items per block, finished in LDS ---------------
+// Order-preserving unsigned key: floats by value with -0 and +0 one key (they compare equal),
+// int32 by value.  Not used for NaN.
+template <bool F>
+__device__ __forceinline__ uint32_t qkey(uint32_t u) {
+    if (!F) return u ^ 0x80000000u;
+    if ((u & 0x7FFFFFFFu) == 0) u = 0;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ---- leaf kernel: one segment of at most 2048 items per block, finished in LDS ---------------
 //
-// Each position carries the start and length of the sub-collection holding it; a round
+// A segment without NaN is sorted by the network (see above).  Otherwise each position
+// carries the start and length of the sub-collection holding it; a round
 // partitions every active sub-collection (length > 1) about its own pivot with one segmented
 // scan of the four class counters, and the children become the next round's sub-collections.
 // Equal items, one-item children and dropped slots are final.
@@ -214,12 +226,43 @@ __global__ __launch_bounds__(QB) void q_leaf(const uint32_t* __restrict__ src, u
     __shared__ uint32_t wflag[QB / 64];
     const Leaf lf = leaves[blockIdx.x];
     const int n = (int)lf.len;
-    for (int i = threadIdx.x; i < n; i += QB) {
-        val[0][i] = src[lf.start + i];
-        sst[0][i] = 0;
-        sln[0][i] = (uint16_t)(n > 1 ? n : QFINAL);
+    // power of two >= n for the sorting network (n <= QLEAF_N)
+    int P = 2;
+    while (P < n) P <<= 1;
+    bool nan = false;
+    for (int i = threadIdx.x; i < P; i += QB) {
+        if (i < n) {
+            const uint32_t x = src[lf.start + i];
+            val[0][i] = x;
+            sst[0][i] = 0;
+            sln[0][i] = (uint16_t)(n > 1 ? n : QFINAL);
+            nan |= F && (x & 0x7FFFFFFFu) > 0x7F800000u;
+            tot[i] = ((uint64_t)qkey<F>(x) << 32) | (uint32_t)i;
+        } else {
+            tot[i] = ~0ull;  // above every key: padding sorts to the end
+        }
     }
-    __syncthreads();
+    if (!__syncthreads_or(nan)) {
+        // No NaN: every filter keeps each item, and items that compare equal (including -0 and
+        // +0) fall on the same side of every pivot, so the listing's recursion of stable
+        // three-way partitions yields the items in ascending order with ties in input order,
+        // i.e. the stable sort.  A bitonic network over (key, position) pairs computes it.
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = threadIdx.x; t < P / 2; t += QB) {
+                    const int i = 2 * j * (t / j) + (t % j), l = i + j;
+                    const uint64_t a = tot[i], c = tot[l];
+                    if ((a > c) == ((i & k) == 0)) {
+                        tot[i] = c;
+                        tot[l] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < n; i += QB) out[lf.start + i] = val[0][(uint32_t)tot[i] & 0xFFFFu];
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p0 = threadIdx.x * LPT;
     unsigned drops = 0;
