@@ -7,17 +7,18 @@
 // reported index is the first violating row of the first probe that has one, and the measure
 // is max |e_i| / b_i.  After RW = [r_v | |r_v|] (N x 8, float64) is written, three streaming
 // passes read B, A and C once each:
-//   1. BW = [B RW_v | |B| RW_(4+v)]       (K x 8)
-//   2. AW = [A BW_v | |A| BW_(4+v)]       (M x 8)
-//   3. C RW_v, compared row by row with AW.
+//   1. BW = [B RW_v | |B| RW_(4+v)]       (K x 8)   } one launch: both need only RW
+//      C RW_v                             (M x 4)   }
+//   2. AW = [A BW_v | |A| BW_(4+v)]       (M x 8), compared row by row with C RW_v.
 // RW and BW are padded with zero rows to a whole number of LDS chunks, so a pass loads its
 // right-hand side with no bounds conditions.
 // Each pass is a row-by-matrix product with a narrow right-hand side.  The columns are split
 // into slices so that a 4096-row pass still has thousands of workgroups: a workgroup stages
 // its slice of the right-hand side in LDS (float64, 512 columns at a time), each of its four
 // waves reads four rows with 16-byte loads per lane and keeps 4 x 8 float64 sums per lane; a
-// second small kernel adds the slices' partial sums in slice order (and, for the last pass,
-// compares).  Every sum is taken in a fixed order, so results repeat from run to run.
+// second small kernel adds B's slices in slice order into BW, and the comparison adds the
+// slices of C and A in the same order itself.  Every sum is taken in a fixed order, so results
+// repeat from run to run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -204,21 +205,22 @@ __device__ __forceinline__ void pc_chunks_pipe(const float* __restrict__ X, int6
 // part[slice][row][c] = sum over the slice's columns j of f_c(X[row][j]) W[j][c], with
 // f_c(x) = x for c < 4 and |x| for c >= 4, W a padded float64 right-hand side with 8 columns
 // (pc_pad(cols) rows, 32-byte aligned).  NW = 4 computes the first four columns only.
+// One workgroup: row block rb, column slice sl.
 template <int NW>
-__global__ __launch_bounds__(256, 2) void pc_part(const float* __restrict__ X, int64_t rows, int64_t cols,
-                                               const double* __restrict__ Wd, int64_t slice_w,
-                                               double* __restrict__ part) {
-    __shared__ __align__(16) double w2[2][NW][PC_CH];
+__device__ __forceinline__ void pc_part_body(const float* __restrict__ X, int64_t rows, int64_t cols,
+                                             const double* __restrict__ Wd, int64_t slice_w,
+                                             double* __restrict__ part, int64_t rb, int64_t sl,
+                                             double (&w2)[2][NW][PC_CH]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * PC_RPB + wave * PC_RPW;
-    const int64_t s0 = (int64_t)blockIdx.y * slice_w, s1 = std::min<int64_t>(cols, s0 + slice_w);
+    const int64_t row0 = rb * PC_RPB + wave * PC_RPW;
+    const int64_t s0 = sl * slice_w, s1 = std::min<int64_t>(cols, s0 + slice_w);
     double acc[PC_RPW][NW];
 #pragma unroll
     for (int r = 0; r < PC_RPW; ++r)
 #pragma unroll
         for (int c = 0; c < NW; ++c) acc[r][c] = 0.0;
     // the same for the whole workgroup (it depends on the block indices only)
-    const bool full = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0) && ((int64_t)blockIdx.x + 1) * PC_RPB <= rows &&
+    const bool full = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0) && (rb + 1) * PC_RPB <= rows &&
                       (s1 - s0) % PC_CH == 0;
     if (full)
         pc_chunks_pipe<NW>(X, cols, Wd, s0, s1, row0, acc, w2);
@@ -253,7 +255,35 @@ __global__ __launch_bounds__(256, 2) void pc_part(const float* __restrict__ X, i
     if ((lane & (64 / NV - 1)) == 0) {
         const int r = idx / NW, c = idx % NW;
         const int64_t row = row0 + r;
-        if (row < rows) part[((int64_t)blockIdx.y * rows + row) * 8 + c] = v[0];
+        if (row < rows) part[(sl * rows + row) * 8 + c] = v[0];
+    }
+}
+
+// A pass: grid (row blocks, slices).
+__global__ __launch_bounds__(256, 2) void pc_part8(const float* __restrict__ X, int64_t rows, int64_t cols,
+                                                   const double* __restrict__ Wd, int64_t slice_w,
+                                                   double* __restrict__ part) {
+    __shared__ __align__(16) double w2[2][8][PC_CH];
+    pc_part_body<8>(X, rows, cols, Wd, slice_w, part, blockIdx.x, blockIdx.y, w2);
+}
+
+// Two passes over the same right-hand side in one launch (they depend on nothing but it):
+// workgroups [0, nb) run the 8-column pass over X8, the rest the 4-column pass over X4; each
+// pass's workgroups are numbered row block fastest, then slice.
+struct PcPass {
+    const float* X;
+    int64_t rows, cols, slice_w, row_blocks;
+    double* part;
+};
+__global__ __launch_bounds__(256, 2) void pc_part_pair(const double* __restrict__ Wd, PcPass p8, PcPass p4, int64_t nb) {
+    __shared__ __align__(16) double w2[2][8][PC_CH];
+    const int64_t i = blockIdx.x;
+    if (i < nb) {
+        pc_part_body<8>(p8.X, p8.rows, p8.cols, Wd, p8.slice_w, p8.part, i % p8.row_blocks, i / p8.row_blocks, w2);
+    } else {
+        const int64_t j = i - nb;
+        pc_part_body<4>(p4.X, p4.rows, p4.cols, Wd, p4.slice_w, p4.part, j % p4.row_blocks, j / p4.row_blocks,
+                        *reinterpret_cast<double(*)[2][4][PC_CH]>(&w2[0][0][0]));
     }
 }
 
@@ -269,20 +299,24 @@ __global__ __launch_bounds__(256) void pc_combine(const double* __restrict__ par
     out[i] = s;
 }
 
-// The last pass: C r_v (sum of the slices) against AW; violations and the largest ratio.
-__global__ __launch_bounds__(256) void pc_compare(const double* __restrict__ part, int64_t slices, int64_t rows,
-                                                  const double* __restrict__ AW, int nvec, double tol,
-                                                  InstResult* res) {
+// The comparison: C r_v and AW = [A BW_v | |A| BW_(4+v)], each the sum of its pass's slices in
+// slice order (the order the combine uses), row by row; violations and the largest ratio.
+__global__ __launch_bounds__(256) void pc_compare(const double* __restrict__ part, int64_t slices,
+                                                  const double* __restrict__ apart, int64_t aslices, int64_t rows,
+                                                  int nvec, double tol, InstResult* res) {
     __shared__ uint64_t wmax[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t row = (int64_t)blockIdx.x * 256 + tid;
     uint64_t worst = 0;
     if (row < rows) {
         for (int v = 0; v < nvec; ++v) {
-            double cr = 0.0;
+            double cr = 0.0, aw = 0.0, b = 0.0;
             for (int64_t k = 0; k < slices; ++k) cr += part[(k * rows + row) * 8 + v];
-            const double e = cr - AW[row * 8 + v];
-            const double b = AW[row * 8 + 4 + v];
+            for (int64_t k = 0; k < aslices; ++k) {
+                aw += apart[(k * rows + row) * 8 + v];
+                b += apart[(k * rows + row) * 8 + 4 + v];
+            }
+            const double e = cr - aw;
             const double ae = e < 0 ? -e : e;
             const bool ok = ae <= tol * b;
             double ratio = b > 0 ? ae / b : (ae == 0 ? 0.0 : __builtin_inf());
@@ -328,8 +362,8 @@ inline PcSplit pc_split(int64_t rows, int64_t cols) {
 size_t sg_product_check_work_bytes(int64_t M, int64_t N, int64_t K) {
     using namespace sg;
     const PcSplit p1 = pc_split(K, N), p2 = pc_split(M, K), p3 = pc_split(M, N);
-    const int64_t part = std::max(p1.slices * K, std::max(p2.slices * M, p3.slices * M));
-    return (size_t)(pc_pad(N) * 8 + pc_pad(K) * 8 + M * 8 + part * 8) * sizeof(double);
+    const int64_t part = std::max(p1.slices * K, p2.slices * M);  // B's partial sums, later A's
+    return (size_t)(pc_pad(N) * 8 + pc_pad(K) * 8 + p3.slices * M * 8 + part * 8) * sizeof(double);
 }
 
 hipError_t sg_launch_product_check(const float* C, const float* A, const float* B, const float* R, int64_t M,
@@ -340,21 +374,21 @@ hipError_t sg_launch_product_check(const float* C, const float* A, const float* 
     if ((uintptr_t)work % 32 != 0) return hipErrorInvalidValue;
     double* RW = work;                      // pc_pad(N) x 8
     double* BW = RW + pc_pad(N) * 8;        // pc_pad(K) x 8
-    double* AW = BW + pc_pad(K) * 8;        // M x 8
-    double* part = AW + M * 8;              // slices x rows x 8
-    auto grid1 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)); };
+    double* cpart = BW + pc_pad(K) * 8;     // C's slices x M x 8
     const PcSplit p1 = pc_split(K, N), p2 = pc_split(M, K), p3 = pc_split(M, N);
+    double* part = cpart + p3.slices * M * 8;  // B's slices x K x 8, then A's slices x M x 8
+    auto grid1 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)); };
     hipLaunchKernelGGL(pc_prep, grid1(pc_pad(N)), dim3(256), 0, s, R, (int)nvec, N, RW, res);
-    hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p1.row_blocks, (unsigned)p1.slices), dim3(256), 0, s, B, K, N,
-                       (const double*)RW, p1.width, part);
+    // B and C against the probes together, then BW, then A against BW, then the comparison
+    const PcPass pb{B, K, N, p1.width, p1.row_blocks, part};
+    const PcPass pcp{C, M, N, p3.width, p3.row_blocks, cpart};
+    const int64_t nb = p1.row_blocks * p1.slices, nc = p3.row_blocks * p3.slices;
+    hipLaunchKernelGGL(pc_part_pair, dim3((unsigned)(nb + nc)), dim3(256), 0, s, (const double*)RW, pb, pcp, nb);
     hipLaunchKernelGGL(pc_combine, grid1(pc_pad(K) * 8), dim3(256), 0, s, (const double*)part, p1.slices, K,
                        pc_pad(K), BW);
-    hipLaunchKernelGGL(pc_part<8>, dim3((unsigned)p2.row_blocks, (unsigned)p2.slices), dim3(256), 0, s, A, M, K,
+    hipLaunchKernelGGL(pc_part8, dim3((unsigned)p2.row_blocks, (unsigned)p2.slices), dim3(256), 0, s, A, M, K,
                        (const double*)BW, p2.width, part);
-    hipLaunchKernelGGL(pc_combine, grid1(M * 8), dim3(256), 0, s, (const double*)part, p2.slices, M, M, AW);
-    hipLaunchKernelGGL(pc_part<4>, dim3((unsigned)p3.row_blocks, (unsigned)p3.slices), dim3(256), 0, s, C, M, N,
-                       (const double*)RW, p3.width, part);
-    hipLaunchKernelGGL(pc_compare, grid1(M), dim3(256), 0, s, (const double*)part, p3.slices, M, (const double*)AW,
-                       (int)nvec, tol, res);
+    hipLaunchKernelGGL(pc_compare, grid1(M), dim3(256), 0, s, (const double*)cpart, p3.slices, (const double*)part,
+                       p2.slices, M, (int)nvec, tol, res);
     return hipGetLastError();
 }
