@@ -15,7 +15,8 @@
 // Large segments are partitioned by three kernels per level over 4096-item tiles: count the
 // four classes per tile, scan the tile counts per segment, then scatter (LDS-staged, so that
 // the writes of a tile are four contiguous runs).  Segments of at most 2048 items are finished
-// by one workgroup each in LDS: without NaN the recursion's result is the stable sort of the
+// by one workgroup each in LDS, all in one launch after the last level (a segment's items stay
+// where its level wrote them): without NaN the recursion's result is the stable sort of the
 // segment, which a bitonic network over (key, position) pairs computes; a segment holding a
 // NaN runs the recursion itself, with the same pivot rule and stable three-way partition, all
 // of the segment's sub-collections partitioned together in each round.
@@ -209,6 +210,7 @@ __device__ __forceinline__ uint32_t qkey(uint32_t u) {
 
 struct Leaf {
     int64_t start, len;
+    const uint32_t* src;  // the buffer holding the segment (the level that produced it wrote it there)
 };
 
 constexpr int LPT = 8;               // positions per thread in the leaf kernel
@@ -216,8 +218,8 @@ constexpr int QLEAF_N = QB * LPT;  // 2048: largest segment finished in LDS
 constexpr uint16_t QFINAL = 0;       // length field of a final position
 
 template <bool F>
-__global__ __launch_bounds__(QB) void q_leaf(const uint32_t* __restrict__ src, uint32_t* __restrict__ out,
-                                             const Leaf* __restrict__ leaves, unsigned long long* __restrict__ dropped) {
+__global__ __launch_bounds__(QB) void q_leaf(uint32_t* __restrict__ out, const Leaf* __restrict__ leaves,
+                                             unsigned long long* __restrict__ dropped) {
     __shared__ uint32_t val[2][QLEAF_N];
     __shared__ uint16_t sst[2][QLEAF_N];  // start of the sub-collection holding the position
     __shared__ uint16_t sln[2][QLEAF_N];  // its length, QFINAL when the position is final
@@ -225,6 +227,7 @@ __global__ __launch_bounds__(QB) void q_leaf(const uint32_t* __restrict__ src, u
     __shared__ uint64_t wsum[QB / 64];
     __shared__ uint32_t wflag[QB / 64];
     const Leaf lf = leaves[blockIdx.x];
+    const uint32_t* __restrict__ src = lf.src;
     const int n = (int)lf.len;
     // power of two >= n for the sorting network (n <= QLEAF_N)
     int P = 2;
@@ -455,11 +458,7 @@ sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, boo
     uint32_t* nxt = bufA;
     std::vector<Seg> active;
     if (m <= QLEAF_N) {
-        leaves.push_back({0, m});
-        SGQ_HIP(hipMemcpyAsync(d_leaf, leaves.data(), sizeof(Leaf), hipMemcpyHostToDevice, st));
-        if (is_f32) hipLaunchKernelGGL(q_leaf<true>, dim3(1), dim3(QB), 0, st, src, dst, d_leaf, d_drop);
-        else hipLaunchKernelGGL(q_leaf<false>, dim3(1), dim3(QB), 0, st, src, dst, d_leaf, d_drop);
-        SGQ_HIP(hipGetLastError());
+        leaves.push_back({0, m, src});
     } else {
         active.push_back({0, m, 0, 0});
     }
@@ -491,7 +490,6 @@ sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, boo
         SGQ_HIP(hipMemcpyAsync(tots.data(), d_tot, segs.size() * sizeof(ulonglong2), hipMemcpyDeviceToHost, st));
         SGQ_HIP(hipStreamSynchronize(st));
         std::vector<Seg> next;
-        leaves.clear();
         for (size_t i = 0; i < segs.size(); ++i) {
             const Seg& s = segs[i];
             const int64_t nL = (uint32_t)tots[i].x, nE = (uint32_t)(tots[i].x >> 32), nG = (uint32_t)tots[i].y;
@@ -499,21 +497,20 @@ sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, boo
             const Seg kids[2] = {{s.start, nL, 0, 0}, {s.start + nL + nE, nG, 0, 0}};
             for (const Seg& k : kids) {
                 if (k.len > QLEAF_N) next.push_back(k);
-                else if (k.len >= 2) leaves.push_back({k.start, k.len});
+                else if (k.len >= 2) leaves.push_back({k.start, k.len, nxt});
             }
-        }
-        if (!leaves.empty()) {
-            // leaves of this level live in nxt, which the next level does not overwrite
-            SGQ_HIP(hipMemcpyAsync(d_leaf, leaves.data(), leaves.size() * sizeof(Leaf), hipMemcpyHostToDevice, st));
-            if (is_f32) hipLaunchKernelGGL(q_leaf<true>, dim3((unsigned)leaves.size()), dim3(QB), 0, st, nxt, dst, d_leaf, d_drop);
-            else hipLaunchKernelGGL(q_leaf<false>, dim3((unsigned)leaves.size()), dim3(QB), 0, st, nxt, dst, d_leaf, d_drop);
-            SGQ_HIP(hipGetLastError());
-            // the leaf table is read by that launch: wait before the next level rewrites it
-            SGQ_HIP(hipStreamSynchronize(st));
         }
         active.swap(next);
         cur = nxt;
         nxt = nxt == bufA ? bufB : bufA;
+    }
+    // Every leaf in one launch: a leaf's items stay where its level wrote them, since later
+    // levels write only the ranges of the segments they partition, which are disjoint from it.
+    if (!leaves.empty()) {
+        SGQ_HIP(hipMemcpyAsync(d_leaf, leaves.data(), leaves.size() * sizeof(Leaf), hipMemcpyHostToDevice, st));
+        if (is_f32) hipLaunchKernelGGL(q_leaf<true>, dim3((unsigned)leaves.size()), dim3(QB), 0, st, dst, d_leaf, d_drop);
+        else hipLaunchKernelGGL(q_leaf<false>, dim3((unsigned)leaves.size()), dim3(QB), 0, st, dst, d_leaf, d_drop);
+        SGQ_HIP(hipGetLastError());
     }
     unsigned long long dleaf = 0;
     SGQ_HIP(hipMemcpyAsync(&dleaf, d_drop, 8, hipMemcpyDeviceToHost, st));
