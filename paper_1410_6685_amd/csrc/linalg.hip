@@ -1,7 +1,8 @@
 // Matrix transposition and matrix-vector products (Section 3.4: transpose, right_multiply,
 // left_multiply; Listing 1).  Both read and write HBM once per element, so they are built for
 // bandwidth: the transpose moves 64 x 64 tiles through LDS (coalesced 16-byte reads of rows,
-// coalesced writes of the transposed rows, a padded tile against bank conflicts); the right
+// coalesced 16-byte writes of the transposed rows, 4-byte accesses in tiles at the matrix's
+// edge or with unaligned rows, a padded tile against bank conflicts); the right
 // product gives each row one wave (16-byte loads along the row, float64 lane sums reduced in a
 // fixed order); the left product has blocks of 256 columns walk a chunk of rows each (coalesced
 // row reads) and adds the chunks' float64 partial sums in chunk order.  Results are the float64
@@ -20,6 +21,29 @@ __global__ __launch_bounds__(256) void t_transpose(const uint32_t* __restrict__ 
                                                    int64_t rows, int64_t cols) {
     __shared__ uint32_t tile[TT][TT + 1];
     const int64_t r0 = (int64_t)blockIdx.y * TT, c0 = (int64_t)blockIdx.x * TT;
+    // a tile inside the matrix with 16-byte aligned rows: 16-byte reads of 16 rows and 16-byte
+    // writes of 16 transposed rows per step (the same for the whole block)
+    if (r0 + TT <= rows && c0 + TT <= cols && rows % 4 == 0 && cols % 4 == 0 &&
+        ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0) {
+        const int tr = threadIdx.x >> 4, tc = (threadIdx.x & 15) * 4;
+        uint4 v[TT / 16];
+#pragma unroll
+        for (int k = 0; k < TT / 16; ++k) v[k] = *reinterpret_cast<const uint4*>(a + (r0 + tr + 16 * k) * cols + c0 + tc);
+#pragma unroll
+        for (int k = 0; k < TT / 16; ++k) {
+            uint32_t* t = &tile[tr + 16 * k][tc];
+            t[0] = v[k].x; t[1] = v[k].y; t[2] = v[k].z; t[3] = v[k].w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TT / 16; ++k) {
+            const int c = tr + 16 * k;  // output row c0 + c, columns r0 + tc .. + 3
+            uint4 o;
+            o.x = tile[tc + 0][c]; o.y = tile[tc + 1][c]; o.z = tile[tc + 2][c]; o.w = tile[tc + 3][c];
+            *reinterpret_cast<uint4*>(b + (c0 + c) * rows + r0 + tc) = o;
+        }
+        return;
+    }
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4 threads
 #pragma unroll
     for (int k = 0; k < TT / 4; ++k) {

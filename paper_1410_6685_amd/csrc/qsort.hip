@@ -250,14 +250,32 @@ __global__ __launch_bounds__(QB) void q_leaf(uint32_t* __restrict__ out, const L
         // +0) fall on the same side of every pivot, so the listing's recursion of stable
         // three-way partitions yields the items in ascending order with ties in input order,
         // i.e. the stable sort.  A bitonic network over (key, position) pairs computes it.
+        // Each step compares the pairs (i, i + j) that differ in bit j of the position, ascending
+        // where bit k of i is clear.  Pairs of one step are disjoint, so a thread loads all of its
+        // pairs before it compares any (their LDS reads in flight together) and writes the
+        // smaller and larger key of each without a branch (keys are distinct: the position is
+        // part of the key).
+        constexpr int PPT = QLEAF_N / 2 / QB;  // pairs per thread at the largest size
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = threadIdx.x; t < P / 2; t += QB) {
-                    const int i = 2 * j * (t / j) + (t % j), l = i + j;
-                    const uint64_t a = tot[i], c = tot[l];
-                    if ((a > c) == ((i & k) == 0)) {
-                        tot[i] = c;
-                        tot[l] = a;
+                uint64_t ka[PPT], kc[PPT];
+                int pi[PPT];
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    const int t = threadIdx.x + q * QB;
+                    pi[q] = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
+                    if (t < P / 2) {
+                        ka[q] = tot[pi[q]];
+                        kc[q] = tot[pi[q] + j];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    if (threadIdx.x + q * QB < P / 2) {
+                        const bool up = (pi[q] & k) == 0;
+                        const uint64_t lo = ka[q] < kc[q] ? ka[q] : kc[q], hi = ka[q] < kc[q] ? kc[q] : ka[q];
+                        tot[pi[q]] = up ? lo : hi;
+                        tot[pi[q] + j] = up ? hi : lo;
                     }
                 }
                 __syncthreads();

@@ -18,7 +18,8 @@ def ctx(sg, request):
     return c
 
 
-@pytest.mark.parametrize("r,c", [(1, 1), (1, 100), (100, 1), (63, 65), (64, 64), (1000, 777), (4096, 4096)])
+@pytest.mark.parametrize("r,c", [(1, 1), (1, 100), (100, 1), (63, 65), (64, 64), (1000, 777), (1000, 1000), (100, 4096),
+                                 (4096, 4096)])
 def test_transpose_bit_exact_in_a_chain(sg, ctx, r, c):
     say("transpose", r, c)
     M = W.normal_f32(r * c, 3).reshape(r, c)
