@@ -84,6 +84,48 @@ def cpu_baseline(n_sample: int) -> dict:
                       f"interpreter, one thread; host {model}, {os.cpu_count()} logical CPUs visible)"}
 
 
+def _cpu_worker(n: int, barrier, queue) -> None:
+    """One core of the all-core baseline: its own instance of the workload (the same seeded
+    recipe at n elements), evaluated by the oracle once every worker is ready."""
+    import oracle
+    import workloads as W
+
+    spec, inp = W.cfg2_spec(n), W.cfg2_inputs(n)
+    barrier.wait()
+    t0 = time.monotonic()  # a system-wide clock: comparable across the workers
+    ref = oracle.evaluate(spec, inp)
+    queue.put((t0, time.monotonic(), ref.values["c"]["value"]))
+
+
+def cpu_baseline_all_cores(n_each: int, workers: int) -> dict:
+    """The oracle on `workers` host cores at once, each on its own instance of n_each elements
+    (child interpreters started fresh, one thread each); rate = all their bytes over the span
+    from the common start to the last finish."""
+    import multiprocessing as mp
+
+    ctx = mp.get_context("spawn")
+    barrier, queue = ctx.Barrier(workers), ctx.Queue()
+    env_keep = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        procs = [ctx.Process(target=_cpu_worker, args=(n_each, barrier, queue)) for _ in range(workers)]
+        for p in procs:
+            p.start()
+        res = [queue.get(timeout=600) for _ in procs]
+        for p in procs:
+            p.join(timeout=60)
+    finally:
+        if env_keep is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_keep
+    span = max(r[1] for r in res) - min(r[0] for r in res)
+    algo = sum(12.0 * n_each + 4.0 * r[2] for r in res)
+    return {"value": round(algo / span / 1e9, 4), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} instances of the cfg2 chain + sortedness at n=2^{n_each.bit_length() - 1}, one per "
+                      f"core ({span:.2f} s from the common start to the last finish)"}
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -615,6 +657,11 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(1 << args.cpu_sample_log2)
+        try:
+            nw = min(16, len(os.sched_getaffinity(0)))  # the host's share of cores for one GPU
+            cpu["all_cores"] = cpu_baseline_all_cores(1 << 23, nw)
+        except Exception as ex:  # the single-thread figure stands on its own
+            cpu["all_cores"] = {"error": str(ex)[:200]}
 
     line = {
         "metric": "fused-chain GB/s (% HBM peak); contract overhead %; learned vs tuned plan",
