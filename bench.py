@@ -103,18 +103,31 @@ def cpu_baseline_all_cores(n_each: int, workers: int) -> dict:
     from the common start to the last finish."""
     import multiprocessing as mp
 
+    import queue as queue_mod
+
     ctx = mp.get_context("spawn")
-    barrier, queue = ctx.Barrier(workers), ctx.Queue()
+    barrier, queue = ctx.Barrier(workers, timeout=300), ctx.Queue()
     env_keep = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
+    procs = []
     try:
         procs = [ctx.Process(target=_cpu_worker, args=(n_each, barrier, queue)) for _ in range(workers)]
         for p in procs:
             p.start()
-        res = [queue.get(timeout=600) for _ in procs]
+        res, t_end = [], time.monotonic() + 600
+        while len(res) < workers:
+            try:
+                res.append(queue.get(timeout=5))
+            except queue_mod.Empty:
+                # a worker that failed never reports: stop waiting for the rest
+                if any(p.exitcode not in (None, 0) for p in procs) or time.monotonic() > t_end:
+                    raise RuntimeError("a CPU baseline worker failed")
         for p in procs:
             p.join(timeout=60)
     finally:
+        for p in procs:
+            if p.is_alive():
+                p.terminate()
         if env_keep is None:
             os.environ.pop("OMP_NUM_THREADS", None)
         else:
