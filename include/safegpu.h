@@ -367,6 +367,7 @@ sg_status sg_batch_release(sg_batch b);
 typedef struct sg_plan { int32_t block, unroll, substeps, split; } sg_plan;
 
 typedef struct sg_mlp_s* sg_mlp;
+typedef struct sg_tunedb_s* sg_tunedb;
 
 sg_status sg_program_split_candidates(sg_program p, int32_t* n);
 /* NULL restores the context defaults. */
@@ -411,6 +412,29 @@ sg_status sg_mlp_get_norm(sg_mlp m, float* mean24, float* scale24, float* lo24, 
 sg_status sg_select_plan(sg_mlp m, sg_program p, const sg_plan* plans, int32_t n, float margin, int32_t* best,
                          float* pred_out, int32_t* fallback);
 
+/* Where a program's launch plan comes from (Section 5: the optimizer chooses how a merged plan
+ * runs).  SG_PLAN_DEFAULT: the context's launch settings; SG_PLAN_AUTOTUNE: the autotuner;
+ * SG_PLAN_LEARNED: the cost model, with the autotuner where it declines; SG_PLAN_SET: a plan
+ * the caller set (sg_program_set_plan, sg_autotune, sg_select_plan). */
+typedef enum sg_plan_source { SG_PLAN_DEFAULT = 0, SG_PLAN_AUTOTUNE = 1, SG_PLAN_LEARNED = 2, SG_PLAN_SET = 3 } sg_plan_source;
+/* From now on, a program of ctx that has no plan of its own gets one before its first
+ * execution or launch: with SG_PLAN_AUTOTUNE the candidates are timed (reps runs each, through
+ * `db` when given: plans already recorded for the program's key are read, not timed) and the
+ * fastest is kept; with SG_PLAN_LEARNED `model` (standardization set) chooses among them
+ * (sg_select_plan with `margin`) and the autotuner decides where it falls back; SG_PLAN_DEFAULT
+ * turns this off.  plans (n, copied; NULL/0 = the built-in candidates: ten launch shapes, plus
+ * two with the first fusion split point when the program has one).  model and db are borrowed:
+ * the caller keeps them alive until the source is set again or the context is destroyed.
+ * Timing runs execute the program (their verdicts are not reported).  sg_program_set_plan(p,
+ * NULL) lets the source choose again.  SG_E_INVALID for an unknown source, bad plans, reps < 1,
+ * a negative margin, a missing model (learned) or a model or database of another context;
+ * SG_E_STATE for a model without standardization. */
+sg_status sg_ctx_set_plan_source(sg_ctx ctx, int32_t source, const sg_plan* plans, int32_t n, int32_t reps,
+                                 sg_mlp model, sg_tunedb db, float margin);
+/* The plan a program runs with (the context's settings where it has none) and how it was
+ * chosen (an sg_plan_source value). */
+sg_status sg_program_plan(sg_program p, sg_plan* plan, int32_t* source);
+
 /* Training data of the cost model, prepared on the device: fits the model's standardization
  * (per feature: float64 mean and population standard deviation, scale = 1 where it is below
  * 1e-6, minimum and maximum) on the raw features X (n x 24, device), writes the standardized
@@ -429,7 +453,6 @@ sg_status sg_mlp_load(sg_ctx ctx, const char* path, sg_mlp* out);
 
 /* ---- the autotuner's timing database ------------------------------------------------------ */
 
-typedef struct sg_tunedb_s* sg_tunedb;
 /* Key of a program on its context's device: a 64-bit hash of its operations, constants,
  * element types, lengths (not the data), clauses, split points and the context's mode, with
  * the device's architecture and compute-unit count.  Equal programs on equal devices get

@@ -41,6 +41,9 @@ class Plan(ctypes.Structure):
         return f"Plan{self.as_tuple()}"
 
 
+PLAN_SOURCES = ("default", "autotune", "learned", "set")  # sg_plan_source values, in order
+
+
 def plans_array(plans):
     arr = (Plan * len(plans))()
     for i, p in enumerate(plans):
@@ -134,6 +137,8 @@ def _sig(lib):
         "sg_tunedb_record": [H, ctypes.c_uint64, H, c_double],
         "sg_autotune_db": [H, H, H, c_int32, c_int32, P(c_int32), P(c_double), P(c_int32)],
         "sg_product_check_noalloc": [H, H, H, H, c_int64, c_int64, c_int64, c_int32, H, H],
+        "sg_ctx_set_plan_source": [H, c_int32, H, c_int32, c_int32, H, H, ctypes.c_float],
+        "sg_program_plan": [H, P(Plan), P(c_int32)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -514,6 +519,13 @@ class Program:
                self.ctx.h)
         return best.value, list(ms), measured.value
 
+    def plan(self):
+        """(the plan the program runs with, how it was chosen: 'default', 'autotune', 'learned'
+        or 'set')."""
+        pl, src = Plan(), c_int32()
+        _check(load().sg_program_plan(self.h, byref(pl), byref(src)), self.ctx.h)
+        return pl.as_tuple(), PLAN_SOURCES[src.value]
+
     def key(self) -> int:
         """Program key of the timing database (operations, constants, types, lengths, clauses,
         mode and device)."""
@@ -800,6 +812,17 @@ class Context:
         self._allocator = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
         _KEEP_ALLOCATORS.append(self._allocator)
         _check(load().sg_ctx_set_allocator(self.h, byref(self._allocator)), self.h)
+
+    def set_plan_source(self, source: str, plans=None, reps: int = 3, model: "Mlp | None" = None,
+                        db: "TuneDB | None" = None, margin: float = 0.01):
+        """Where programs without a plan of their own get one before their first execution:
+        'default', 'autotune' or 'learned' (model required; the autotuner where it declines).
+        The model and database must outlive their use by this context."""
+        arr = plans_array(plans) if plans else None
+        _check(load().sg_ctx_set_plan_source(self.h, PLAN_SOURCES.index(source), arr, len(plans) if plans else 0,
+                                             reps, model.h if model is not None else None,
+                                             db.h if db is not None else None, margin), self.h)
+        self._plan_refs = (model, db)  # kept alive while the context may use them
 
     def set_specialize(self, on: bool):
         _check(load().sg_ctx_set_specialize(self.h, int(on)), self.h)

@@ -676,6 +676,8 @@ sg_status sg_program_split(sg_program p, sg_node n) {
 sg_status sg_program_execute(sg_program p, sg_verdict* verdicts, int32_t cap, int32_t* nverdicts) {
     if (!p) return fail(nullptr, SG_E_INVALID, "execute: NULL program");
     if (cap < 0 || (cap > 0 && !verdicts)) return fail(p->ctx, SG_E_INVALID, "execute: bad verdict buffer");
+    const sg_status ps = apply_plan_source(p);
+    if (ps != SG_OK) return ps;
     return execute_program(p, verdicts, cap, nverdicts);
 }
 
@@ -683,6 +685,8 @@ sg_status sg_program_launch(sg_program p) {
     if (!p) return fail(nullptr, SG_E_INVALID, "launch: NULL program");
     if ((int)p->pending.size() >= sg_program_s::kMaxPending)
         return fail(p->ctx, SG_E_STATE, "launch: too many pending launches; wait for one first");
+    const sg_status ps = apply_plan_source(p);  // only before the first pending launch
+    if (ps != SG_OK) return ps;
     // a plan that needs rebuilding would no longer match the pending launches' results
     if (!p->pending.empty() && (!p->plan.valid || p->plan.generation != p->ctx->generation))
         return fail(p->ctx, SG_E_STATE, "launch: the program or its context changed while launches are pending");

@@ -252,6 +252,7 @@ sg_status sg_autotune_db(sg_program p, sg_tunedb db, const sg_plan* plans, int32
         if (ms[i] < ms[b]) b = i;
     sg_status st = sg_program_set_plan(p, &plans[b]);
     if (st != SG_OK) return st;
+    p->plan_from = SG_PLAN_AUTOTUNE;
     *best = b;
     if (ms_out) std::memcpy(ms_out, ms.data(), sizeof(double) * n);
     if (measured) *measured = (int32_t)todo.size();
@@ -318,3 +319,7 @@ sg_status sg_mlp_load(sg_ctx ctx, const char* path, sg_mlp* out) {
 }
 
 }  // extern "C"
+
+namespace sgrt {
+sg_ctx_s* tunedb_ctx(const sg_tunedb_s* db) { return db->ctx; }
+}  // namespace sgrt

@@ -58,6 +58,14 @@ struct sg_ctx_s {
     int unroll = 2;
     int substeps = 8;
     int batch_substeps = 1;  // sub-tiles per tile of batched launches
+    // where programs without a plan of their own get one (sg_ctx_set_plan_source); the model
+    // and the timing database are the caller's, borrowed while they are set
+    int plan_source = SG_PLAN_DEFAULT;
+    std::vector<sg_plan> plan_cands;  // empty: the built-in candidates
+    struct sg_mlp_s* plan_model = nullptr;
+    struct sg_tunedb_s* plan_db = nullptr;
+    float plan_margin = 0.01f;
+    int plan_reps = 3;
     uint32_t epoch = 0;  // host epoch of direct launches
     int last_grid = 0, last_block = 0, last_unroll = 0, last_substeps = 0;  // last streaming launch
     size_t last_lds = 0;
@@ -202,6 +210,11 @@ struct ExecSlot {
 };
 
 sg_status fail(sg_ctx_s* ctx, sg_status st, const std::string& msg);
+// the context a timing database belongs to (persist.hip)
+sg_ctx_s* tunedb_ctx(const sg_tunedb_s* db);
+// a program with no plan of its own gets one from its context's plan source, before its
+// first execution or launch (tune.hip)
+sg_status apply_plan_source(sg_program_s* p);
 // SG_OK when [p, p + bytes) lies inside one device allocation of the calling process
 sg_status check_device_range(sg_ctx_s* ctx, const void* p, size_t bytes, const char* what);
 sg_status hip_fail(sg_ctx_s* ctx, hipError_t e, const char* what);
@@ -269,6 +282,8 @@ struct sg_program_s {
     // launch plan chosen for this program (autotuner / selector); 0 = the context default
     int block = 0, unroll = 0, substeps = 0;
     sg_node_s* plan_split = nullptr;  // extra fusion split point of the plan
+    int plan_from = SG_PLAN_DEFAULT;  // how the plan was chosen (SG_PLAN_*)
+    bool plan_auto_tried = false;     // the context's plan source has been applied
     sgrt::Plan plan;
     int32_t next_contract = 0;
     // asynchronous launches: slots in use, oldest first (the program is not changed meanwhile)

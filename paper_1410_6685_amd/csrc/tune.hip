@@ -182,12 +182,15 @@ sg_status sg_program_set_plan(sg_program p, const sg_plan* plan) {
         p->block = p->unroll = p->substeps = 0;
         p->plan_split = nullptr;
         p->plan.valid = false;
+        p->plan_from = SG_PLAN_DEFAULT;
+        p->plan_auto_tried = false;  // the context's plan source applies again
         return SG_OK;
     }
     if (!valid_plan(plan)) return fail(p->ctx, SG_E_INVALID, "set_plan: block 64..1024 (x64), unroll 1/2/4, substeps 1..64");
     auto cands = split_candidates(p);
     ApplyPlan ap(p, plan, cands);
     ap.keep();
+    p->plan_from = SG_PLAN_SET;
     return SG_OK;
 }
 
@@ -236,7 +239,62 @@ sg_status sg_autotune(sg_program p, const sg_plan* plans, int32_t n, int32_t rep
     int b = (int)(std::min_element(ms.begin(), ms.begin() + n) - ms.begin());
     if (best) *best = b;
     if (ms_out) std::memcpy(ms_out, ms.data(), n * sizeof(double));
-    return sg_program_set_plan(p, &plans[b]);
+    st = sg_program_set_plan(p, &plans[b]);
+    if (st == SG_OK) p->plan_from = SG_PLAN_AUTOTUNE;
+    return st;
+}
+
+// The built-in candidate plans of a plan source: ten launch shapes, and two with the first
+// fusion split point when the program has one.
+static std::vector<sg_plan> builtin_plans(sg_program_s* p) {
+    std::vector<sg_plan> c = {{64, 1, 8, -1},  {128, 2, 8, -1}, {256, 1, 8, -1}, {256, 2, 8, -1},
+                              {256, 4, 8, -1}, {256, 2, 32, -1}, {512, 2, 4, -1}, {512, 4, 8, -1},
+                              {1024, 1, 4, -1}, {1024, 2, 8, -1}};
+    if (!split_candidates(p).empty()) {
+        c.push_back({256, 2, 8, 0});
+        c.push_back({256, 4, 8, 0});
+    }
+    return c;
+}
+
+sg_status sg_ctx_set_plan_source(sg_ctx ctx, int32_t source, const sg_plan* plans, int32_t n, int32_t reps,
+                                 sg_mlp model, sg_tunedb db, float margin) {
+    if (!ctx) return fail(nullptr, SG_E_INVALID, "set_plan_source: NULL context");
+    if (source < SG_PLAN_DEFAULT || source > SG_PLAN_LEARNED)
+        return fail(ctx, SG_E_INVALID, "set_plan_source: source must be SG_PLAN_DEFAULT, _AUTOTUNE or _LEARNED");
+    if (n < 0 || (n > 0 && !plans) || reps < 1 || !(margin >= 0.0f))
+        return fail(ctx, SG_E_INVALID, "set_plan_source: bad plans, repetitions or margin");
+    for (int i = 0; i < n; ++i)
+        if (!valid_plan(&plans[i])) return fail(ctx, SG_E_INVALID, "set_plan_source: invalid plan");
+    if (source == SG_PLAN_LEARNED) {
+        if (!model) return fail(ctx, SG_E_INVALID, "set_plan_source: the learned source needs a model");
+        if (model->ctx != ctx) return fail(ctx, SG_E_INVALID, "set_plan_source: model of another context");
+        if (!model->norm_set) return fail(ctx, SG_E_STATE, "set_plan_source: the model has no standardization");
+    }
+    if (db && tunedb_ctx(db) != ctx) return fail(ctx, SG_E_INVALID, "set_plan_source: database of another context");
+    ctx->plan_source = source;
+    ctx->plan_cands.assign(plans, plans + n);
+    ctx->plan_model = source == SG_PLAN_LEARNED ? model : nullptr;
+    ctx->plan_db = source == SG_PLAN_DEFAULT ? nullptr : db;
+    ctx->plan_margin = margin;
+    ctx->plan_reps = reps;
+    return SG_OK;
+}
+
+sg_status sg_program_plan(sg_program p, sg_plan* plan, int32_t* source) {
+    if (!p || !plan || !source) return fail(p ? p->ctx : nullptr, SG_E_INVALID, "program_plan: NULL argument");
+    const sg_ctx_s* ctx = p->ctx;
+    plan->block = p->block ? p->block : ctx->block;
+    plan->unroll = p->unroll ? p->unroll : ctx->unroll;
+    plan->substeps = p->substeps ? p->substeps : ctx->substeps;
+    plan->split = -1;
+    if (p->plan_split) {
+        auto cands = split_candidates(p);
+        for (size_t i = 0; i < cands.size(); ++i)
+            if (cands[i] == p->plan_split) plan->split = (int32_t)i;
+    }
+    *source = p->plan_from;
+    return SG_OK;
 }
 
 }  // extern "C"
@@ -309,8 +367,35 @@ sg_status sg_select_plan(sg_mlp m, sg_program p, const sg_plan* plans, int32_t n
     *best = order[0];
     *fallback = ood || (n > 1 && Y[order[1]] - Y[order[0]] < margin) ? 1 : 0;
     if (pred_out) std::memcpy(pred_out, Y.data(), (size_t)n * 4);
-    if (!*fallback) return sg_program_set_plan(p, &plans[*best]);
-    return SG_OK;
+    if (*fallback) return SG_OK;
+    st = sg_program_set_plan(p, &plans[*best]);
+    if (st == SG_OK) p->plan_from = SG_PLAN_LEARNED;
+    return st;
 }
 
+
 }  // extern "C"
+
+namespace sgrt {
+
+// Before a program's first execution or launch: a program with no plan of its own gets one from
+// its context's plan source (once; sg_program_set_plan(p, NULL) re-arms it).  The autotuner
+// runs the program itself (through the internal execution path) on every candidate.
+sg_status apply_plan_source(sg_program_s* p) {
+    sg_ctx_s* ctx = p->ctx;
+    if (ctx->plan_source == SG_PLAN_DEFAULT || p->plan_auto_tried || p->block != 0 || !p->pending.empty())
+        return SG_OK;
+    p->plan_auto_tried = true;
+    const std::vector<sg_plan> c = ctx->plan_cands.empty() ? builtin_plans(p) : ctx->plan_cands;
+    const int32_t n = (int32_t)c.size();
+    int32_t best = 0, fallback = 1;
+    if (ctx->plan_source == SG_PLAN_LEARNED) {
+        sg_status st = sg_select_plan(ctx->plan_model, p, c.data(), n, ctx->plan_margin, &best, nullptr, &fallback);
+        if (st != SG_OK || !fallback) return st;
+    }
+    // the autotuner: the source itself, or the learned source's fallback
+    if (ctx->plan_db) return sg_autotune_db(p, ctx->plan_db, c.data(), n, ctx->plan_reps, &best, nullptr, nullptr);
+    return sg_autotune(p, c.data(), n, ctx->plan_reps, &best, nullptr);
+}
+
+}  // namespace sgrt

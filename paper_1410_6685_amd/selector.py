@@ -18,7 +18,9 @@ import numpy as np
 from . import Mlp, Plan
 
 # Candidate plans (block, unroll, sub-tiles per tile, split): launch shapes across the useful
-# range, and the first fusion split where a chain offers one.
+# range, and the first fusion split where a chain offers one -- the library's built-in
+# candidates of a context plan source (sg_ctx_set_plan_source), so that a model trained on
+# them chooses among the same plans there.
 DEFAULT_PLANS = [(64, 1, 8, -1), (128, 2, 8, -1), (256, 1, 8, -1), (256, 2, 8, -1), (256, 4, 8, -1),
                  (256, 2, 32, -1), (512, 2, 4, -1), (512, 4, 8, -1), (1024, 1, 4, -1), (1024, 2, 8, -1)]
 SPLIT_PLANS = [(256, 2, 8, 0), (256, 4, 8, 0)]

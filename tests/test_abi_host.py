@@ -53,6 +53,8 @@ def test_misuse_is_rejected_without_gpu(lib):
     assert L.sg_pred_cmp(42, 0.0, byref(h)) == 1
     assert L.sg_map(None, None, byref(h)) == 1
     assert L.sg_program_execute(None, None, 0, None) == 1
+    assert L.sg_ctx_set_plan_source(None, 1, None, 0, 3, None, None, 0.01) == 1
+    assert L.sg_program_plan(None, None, None) == 1
     assert L.sg_fn_affine(2.0, 1.0, byref(h)) == 0
     f = h.value
     g = c_void_p()

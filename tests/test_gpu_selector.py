@@ -100,6 +100,64 @@ def test_learned_plan_beats_default_and_tracks_autotuner(sg, ctx, buffers, tmp_p
         assert np.array_equal(a, b)
     for b, plans in zip(test_b[:30], te.plans[:30]):
         assert again.select(b.program, plans, 0.01)[0] == net.select(b.program, plans, 0.01)[0]
+    # The context's learned plan source: programs without a plan of their own get the model's
+    # choice among the built-in candidates (the selector's) before their first execution, or
+    # the autotuner's where the model declines.
+    fresh = programs(sg, ctx, buffers, 40, 62)  # the first 40 held-out chains again
+    ctx.set_plan_source("learned", model=net, reps=2)
+    try:
+        learned = 0
+        for f, b in zip(fresh, test_b[:40]):
+            plans = selector.candidate_plans(b.program)
+            status, _ = f.program.execute()
+            assert status in ("ok", "post_violated", "pre_violated")
+            plan, source = f.program.plan()
+            b.program.set_plan(None)
+            best, _, fallback = net.select(b.program, plans, 0.01)
+            if fallback:
+                assert source == "autotune" and plan in plans
+            else:
+                assert (source, plan) == ("learned", plans[best])
+                learned += 1
+        say("plan source: learned for", learned, "of", len(fresh))
+        assert learned > 0
+    finally:
+        ctx.set_plan_source("default")
+
+
+def test_autotune_plan_source(sg, ctx, buffers, tmp_path):
+    """The context's autotune source: a program without a plan gets the fastest candidate
+    before its first execution (through the timing database), an explicitly set plan is kept,
+    and clearing a program's plan lets the source choose again."""
+    plans = [(256, 2, 8, -1), (256, 4, 2, -1), (512, 2, 4, -1)]
+    db = sg.TuneDB(ctx, str(tmp_path / "src.txt"))
+    ctx.set_plan_source("autotune", plans=plans, reps=2, db=db)
+    try:
+        bs = programs(sg, ctx, buffers, 4, 73)
+        for b in bs:
+            assert b.program.plan()[1] == "default"
+            b.program.execute()
+            plan, source = b.program.plan()
+            assert source == "autotune" and plan in plans
+            ms = [db.lookup(b.program.key(), p) for p in plans]
+            assert all(m is not None for m in ms) and plan == plans[int(np.argmin(ms))]
+        kept = programs(sg, ctx, buffers, 1, 74)[0]
+        kept.program.set_plan((128, 1, 4, -1))
+        kept.program.execute()
+        assert kept.program.plan() == ((128, 1, 4, -1), "set")
+        kept.program.set_plan(None)
+        kept.program.launch()
+        kept.program.wait()
+        assert kept.program.plan()[1] == "autotune"
+        with pytest.raises(sg.SafeGPUError):
+            ctx.set_plan_source("learned")  # no model
+        with pytest.raises(sg.SafeGPUError):
+            ctx.set_plan_source("autotune", plans=[(100, 2, 8, -1)])  # not a multiple of 64
+    finally:
+        ctx.set_plan_source("default")
+    other = programs(sg, ctx, buffers, 1, 75)[0]
+    other.program.execute()
+    assert other.program.plan()[1] == "default"
 
 
 def test_tunedb_reuses_timings_and_resumes(sg, ctx, buffers, tmp_path):
