@@ -98,8 +98,18 @@ __global__ __launch_bounds__(QB) void q_count(const uint32_t* __restrict__ cur, 
     const Seg s = segs[tile_seg[t]];
     const uint32_t p = cur[s.start + s.len / 2];
     const int64_t lo = (t - s.tile0) * QTE, hi = std::min<int64_t>(lo + QTE, s.len);
+    // the tile's QPT loads per thread are issued together (a fixed count, guarded), not one
+    // round trip after another
+    uint32_t x[QPT];
+#pragma unroll
+    for (int q = 0; q < QPT; ++q) {
+        const int64_t i = lo + threadIdx.x + q * QB;
+        x[q] = i < hi ? cur[s.start + i] : 0u;
+    }
     uint64_t c = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += QB) c += one_hot(qclass<F>(cur[s.start + i], p));
+#pragma unroll
+    for (int q = 0; q < QPT; ++q)
+        if (lo + threadIdx.x + q * QB < hi) c += one_hot(qclass<F>(x[q], p));
     uint64_t tot;
     (void)block_excl_sum(c, wsum, &tot);
     if (threadIdx.x == 0) tile_cnt[t] = make_uint4(field(tot, 0), field(tot, 1), field(tot, 2), field(tot, 3));
@@ -144,7 +154,19 @@ __global__ __launch_bounds__(QB) void q_scatter(const uint32_t* __restrict__ cur
     const uint32_t p = cur[s.start + s.len / 2];
     const int64_t lo = (t - s.tile0) * QTE;
     const int cnt = (int)std::min<int64_t>(QTE, s.len - lo);
-    for (int i = threadIdx.x; i < cnt; i += QB) v[(i / QPT) * QPAD + i % QPT] = cur[s.start + lo + i];
+    {
+        uint32_t x[QPT];  // all loads in flight before the first is stored
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int i = threadIdx.x + q * QB;
+            x[q] = i < cnt ? cur[s.start + lo + i] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < QPT; ++q) {
+            const int i = threadIdx.x + q * QB;
+            if (i < cnt) v[(i / QPT) * QPAD + i % QPT] = x[q];
+        }
+    }
     __syncthreads();
     // this thread's items: positions tid*16 .. tid*16+15 of the tile, in order
     const int first = threadIdx.x * QPT;
@@ -233,9 +255,18 @@ __global__ __launch_bounds__(QB) void q_leaf(uint32_t* __restrict__ out, const L
     int P = 2;
     while (P < n) P <<= 1;
     bool nan = false;
-    for (int i = threadIdx.x; i < P; i += QB) {
+    uint32_t xs[LPT];  // the segment's loads in flight together
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        const int i = threadIdx.x + q * QB;
+        xs[q] = i < n ? src[lf.start + i] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        const int i = threadIdx.x + q * QB;
+        if (i >= P) continue;
         if (i < n) {
-            const uint32_t x = src[lf.start + i];
+            const uint32_t x = xs[q];
             val[0][i] = x;
             sst[0][i] = 0;
             sln[0][i] = (uint16_t)(n > 1 ? n : QFINAL);
