@@ -224,7 +224,7 @@ __device__ __forceinline__ uint32_t qkey(uint32_t u) {
 
 // ---- leaf kernel: one segment of at most 2048 items per block, finished in LDS ---------------
 //
-// A segment without NaN is sorted by the network (see above).  Otherwise each position
+// Leaves holding a NaN (listed by q_leaf_net) run the recursion: each position
 // carries the start and length of the sub-collection holding it; a round
 // partitions every active sub-collection (length > 1) about its own pivot with one segmented
 // scan of the four class counters, and the children become the next round's sub-collections.
@@ -239,15 +239,13 @@ constexpr int LPT = 8;               // positions per thread in the leaf kernel
 constexpr int QLEAF_N = QB * LPT;  // 2048: largest segment finished in LDS
 constexpr uint16_t QFINAL = 0;       // length field of a final position
 
+// The leaves without NaN: a bitonic network over (key, position) pairs in 24 KiB of LDS.  A leaf
+// holding a NaN is left for q_leaf: its index goes to `nan_list`.
 template <bool F>
-__global__ __launch_bounds__(QB) void q_leaf(uint32_t* __restrict__ out, const Leaf* __restrict__ leaves,
-                                             unsigned long long* __restrict__ dropped) {
-    __shared__ uint32_t val[2][QLEAF_N];
-    __shared__ uint16_t sst[2][QLEAF_N];  // start of the sub-collection holding the position
-    __shared__ uint16_t sln[2][QLEAF_N];  // its length, QFINAL when the position is final
-    __shared__ uint64_t tot[QLEAF_N];     // class totals of a sub-collection, at its start
-    __shared__ uint64_t wsum[QB / 64];
-    __shared__ uint32_t wflag[QB / 64];
+__global__ __launch_bounds__(QB) void q_leaf_net(uint32_t* __restrict__ out, const Leaf* __restrict__ leaves,
+                                                 uint32_t* __restrict__ nan_list, uint32_t* __restrict__ nan_count) {
+    __shared__ uint32_t val[QLEAF_N];
+    __shared__ uint64_t tot[QLEAF_N];
     const Leaf lf = leaves[blockIdx.x];
     const uint32_t* __restrict__ src = lf.src;
     const int n = (int)lf.len;
@@ -266,55 +264,83 @@ __global__ __launch_bounds__(QB) void q_leaf(uint32_t* __restrict__ out, const L
         const int i = threadIdx.x + q * QB;
         if (i >= P) continue;
         if (i < n) {
-            const uint32_t x = xs[q];
-            val[0][i] = x;
-            sst[0][i] = 0;
-            sln[0][i] = (uint16_t)(n > 1 ? n : QFINAL);
-            nan |= F && (x & 0x7FFFFFFFu) > 0x7F800000u;
-            tot[i] = ((uint64_t)qkey<F>(x) << 32) | (uint32_t)i;
+            val[i] = xs[q];
+            nan |= F && (xs[q] & 0x7FFFFFFFu) > 0x7F800000u;
+            tot[i] = ((uint64_t)qkey<F>(xs[q]) << 32) | (uint32_t)i;
         } else {
             tot[i] = ~0ull;  // above every key: padding sorts to the end
         }
     }
-    if (!__syncthreads_or(nan)) {
-        // No NaN: every filter keeps each item, and items that compare equal (including -0 and
-        // +0) fall on the same side of every pivot, so the listing's recursion of stable
-        // three-way partitions yields the items in ascending order with ties in input order,
-        // i.e. the stable sort.  A bitonic network over (key, position) pairs computes it.
-        // Each step compares the pairs (i, i + j) that differ in bit j of the position, ascending
-        // where bit k of i is clear.  Pairs of one step are disjoint, so a thread loads all of its
-        // pairs before it compares any (their LDS reads in flight together) and writes the
-        // smaller and larger key of each without a branch (keys are distinct: the position is
-        // part of the key).
-        constexpr int PPT = QLEAF_N / 2 / QB;  // pairs per thread at the largest size
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                uint64_t ka[PPT], kc[PPT];
-                int pi[PPT];
-#pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    const int t = threadIdx.x + q * QB;
-                    pi[q] = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
-                    if (t < P / 2) {
-                        ka[q] = tot[pi[q]];
-                        kc[q] = tot[pi[q] + j];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    if (threadIdx.x + q * QB < P / 2) {
-                        const bool up = (pi[q] & k) == 0;
-                        const uint64_t lo = ka[q] < kc[q] ? ka[q] : kc[q], hi = ka[q] < kc[q] ? kc[q] : ka[q];
-                        tot[pi[q]] = up ? lo : hi;
-                        tot[pi[q] + j] = up ? hi : lo;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (int i = threadIdx.x; i < n; i += QB) out[lf.start + i] = val[0][(uint32_t)tot[i] & 0xFFFFu];
+    if (__syncthreads_or(nan)) {
+        if (threadIdx.x == 0) nan_list[atomicAdd(nan_count, 1u)] = blockIdx.x;
         return;
     }
+    // No NaN: every filter keeps each item, and items that compare equal (including -0 and
+    // +0) fall on the same side of every pivot, so the listing's recursion of stable
+    // three-way partitions yields the items in ascending order with ties in input order,
+    // i.e. the stable sort.  A bitonic network over (key, position) pairs computes it.
+    // Each step compares the pairs (i, i + j) that differ in bit j of the position, ascending
+    // where bit k of i is clear.  Pairs of one step are disjoint, so a thread loads all of its
+    // pairs before it compares any (their LDS reads in flight together) and writes the
+    // smaller and larger key of each without a branch (keys are distinct: the position is
+    // part of the key).
+    constexpr int PPT = QLEAF_N / 2 / QB;  // pairs per thread at the largest size
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint64_t ka[PPT], kc[PPT];
+            int pi[PPT];
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const int t = threadIdx.x + q * QB;
+                pi[q] = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // j is a power of two
+                if (t < P / 2) {
+                    ka[q] = tot[pi[q]];
+                    kc[q] = tot[pi[q] + j];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (threadIdx.x + q * QB < P / 2) {
+                    const bool up = (pi[q] & k) == 0;
+                    const uint64_t lo = ka[q] < kc[q] ? ka[q] : kc[q], hi = ka[q] < kc[q] ? kc[q] : ka[q];
+                    tot[pi[q]] = up ? lo : hi;
+                    tot[pi[q] + j] = up ? hi : lo;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += QB) out[lf.start + i] = val[(uint32_t)tot[i] & 0xFFFFu];
+}
+
+template <bool F>
+__global__ __launch_bounds__(QB) void q_leaf(uint32_t* __restrict__ out, const Leaf* __restrict__ leaves,
+                                             const uint32_t* __restrict__ list, unsigned long long* __restrict__ dropped) {
+    __shared__ uint32_t val[2][QLEAF_N];
+    __shared__ uint16_t sst[2][QLEAF_N];  // start of the sub-collection holding the position
+    __shared__ uint16_t sln[2][QLEAF_N];  // its length, QFINAL when the position is final
+    __shared__ uint64_t tot[QLEAF_N];     // class totals of a sub-collection, at its start
+    __shared__ uint64_t wsum[QB / 64];
+    __shared__ uint32_t wflag[QB / 64];
+    const Leaf lf = leaves[list[blockIdx.x]];
+    const uint32_t* __restrict__ src = lf.src;
+    const int n = (int)lf.len;
+    uint32_t xs[LPT];  // the segment's loads in flight together
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        const int i = threadIdx.x + q * QB;
+        xs[q] = i < n ? src[lf.start + i] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+        const int i = threadIdx.x + q * QB;
+        if (i < n) {
+            val[0][i] = xs[q];
+            sst[0][i] = 0;
+            sln[0][i] = (uint16_t)(n > 1 ? n : QFINAL);
+        }
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p0 = threadIdx.x * LPT;
     unsigned drops = 0;
@@ -477,7 +503,9 @@ sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, boo
     const size_t b_cnt = (size_t)max_tiles * sizeof(uint4), b_tot = (size_t)max_segs * sizeof(ulonglong2);
     const size_t b_leaf = (size_t)std::min<int64_t>(max_leaves, m / 2 + 2) * sizeof(Leaf);
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t total = 2 * up(b_items) + up(b_segs) + up(b_tseg) + 2 * up(b_cnt) + up(b_tot) + up(b_leaf) + 256;
+    const size_t b_nanl = (size_t)std::min<int64_t>(max_leaves, m / 2 + 2) * 4;
+    const size_t total = 2 * up(b_items) + up(b_segs) + up(b_tseg) + 2 * up(b_cnt) + up(b_tot) + up(b_leaf) +
+                         up(b_nanl) + 256;
     char* w = (char*)dev_alloc(ctx, total);
     if (!w) return fail(ctx, SG_E_OOM, "quicksort: work memory");
     char* c = w;
@@ -489,14 +517,16 @@ sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, boo
     uint4* d_off = (uint4*)c; c += up(b_cnt);
     ulonglong2* d_tot = (ulonglong2*)c; c += up(b_tot);
     Leaf* d_leaf = (Leaf*)c; c += up(b_leaf);
+    uint32_t* d_nanl = (uint32_t*)c; c += up(b_nanl);  // leaves holding a NaN
     unsigned long long* d_drop = (unsigned long long*)c;
+    uint32_t* d_nanc = (uint32_t*)(d_drop + 1);          // their number
     auto done = [&](sg_status s) { dev_free(ctx, w); return s; };
 #define SGQ_HIP(call)                                                                  \
     do {                                                                               \
         hipError_t _e = (call);                                                        \
         if (_e != hipSuccess) return done(sgrt::hip_fail(ctx, _e, #call));            \
     } while (0)
-    SGQ_HIP(hipMemsetAsync(d_drop, 0, 8, st));
+    SGQ_HIP(hipMemsetAsync(d_drop, 0, 16, st));
     std::vector<Seg> segs;
     std::vector<int32_t> tseg;
     std::vector<Leaf> leaves;
@@ -557,9 +587,20 @@ sg_status run_quicksort(sg_ctx_s* ctx, const void* in, void* out, int64_t m, boo
     // levels write only the ranges of the segments they partition, which are disjoint from it.
     if (!leaves.empty()) {
         SGQ_HIP(hipMemcpyAsync(d_leaf, leaves.data(), leaves.size() * sizeof(Leaf), hipMemcpyHostToDevice, st));
-        if (is_f32) hipLaunchKernelGGL(q_leaf<true>, dim3((unsigned)leaves.size()), dim3(QB), 0, st, dst, d_leaf, d_drop);
-        else hipLaunchKernelGGL(q_leaf<false>, dim3((unsigned)leaves.size()), dim3(QB), 0, st, dst, d_leaf, d_drop);
+        const dim3 g((unsigned)leaves.size());
+        if (is_f32) hipLaunchKernelGGL(q_leaf_net<true>, g, dim3(QB), 0, st, dst, d_leaf, d_nanl, d_nanc);
+        else hipLaunchKernelGGL(q_leaf_net<false>, g, dim3(QB), 0, st, dst, d_leaf, d_nanl, d_nanc);
         SGQ_HIP(hipGetLastError());
+        // the leaves holding a NaN run the listing's recursion (the order of the list is free:
+        // each leaf writes only its own range)
+        uint32_t nanc = 0;
+        SGQ_HIP(hipMemcpyAsync(&nanc, d_nanc, 4, hipMemcpyDeviceToHost, st));
+        SGQ_HIP(hipStreamSynchronize(st));
+        if (nanc > 0) {
+            if (is_f32) hipLaunchKernelGGL(q_leaf<true>, dim3(nanc), dim3(QB), 0, st, dst, d_leaf, d_nanl, d_drop);
+            else hipLaunchKernelGGL(q_leaf<false>, dim3(nanc), dim3(QB), 0, st, dst, d_leaf, d_nanl, d_drop);
+            SGQ_HIP(hipGetLastError());
+        }
     }
     unsigned long long dleaf = 0;
     SGQ_HIP(hipMemcpyAsync(&dleaf, d_drop, 8, hipMemcpyDeviceToHost, st));
